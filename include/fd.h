@@ -1,0 +1,168 @@
+/*
+ * fd.h -- C ABI of libfd, the MI355X (gfx950) Fast-Diagonalization library.
+ *
+ * The library applies the inverse of Kronecker-sum preconditioner blocks
+ *
+ *     P = sum_i w_i (M_d (x) ... (x) K_i (x) ... (x) M_1)          (1)
+ *
+ * (Montardini, Sangalli, Tani 2018, Sec. 5 eq. prec3D_TH for the velocity
+ * blocks P_V,k, eq. precQ for the pressure block P_Q = M_d (x) .. (x) M_1,
+ * and the Appendix for the coefficient-aware blocks) by the Fast
+ * Diagonalization method of Sec. 5.2, Algorithm 1:
+ *
+ *     K_i U_i = M_i U_i D_i,  U_i^T M_i U_i = I                     (eq. eig_dec)
+ *     z = (U_d (x) .. (x) U_1) Lambda^{-1} (U_d (x) .. (x) U_1)^T r,
+ *     Lambda = sum_i w_i (I (x) .. (x) D_i (x) .. (x) I).
+ *
+ * Optionally with the diagonal scaling of Sec. 6: P^G = D^{1/2} P D^{1/2},
+ * [D]_ii = [target]_ii / [P]_ii, so z = D^{-1/2} P^{-1} D^{-1/2} r.
+ *
+ * Vector layout (Sec. 2.3, definition of vec): a block of sizes
+ * (n_1, .., n_d) is a vector of prod(n_i) elements with i_1 fastest.
+ *
+ * Conventions for every call:
+ *  - Host pointers are read during the call only; the caller keeps ownership
+ *    and may free them on return.
+ *  - Device pointers are caller-owned device memory (e.g. from torch); the
+ *    library never frees them.
+ *  - Every call returns an fd_status. On failure a thread-local message is
+ *    available from fd_last_error(); no exception crosses the ABI.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream). Work
+ *    is enqueued asynchronously; execution errors surface at the caller's
+ *    synchronisation.
+ */
+#ifndef FD_H_
+#define FD_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FD_OK = 0,
+  FD_E_ARG = 1,          /* invalid argument: sizes, NULL pointers, asymmetric input */
+  FD_E_NOTSPD = 2,       /* M not positive definite, or an eigenvalue sum <= 0 */
+  FD_E_NOMEM = 3,        /* host or device allocation failed */
+  FD_E_HIP = 4,          /* a HIP runtime call failed (message names it) */
+  FD_E_UNSUPPORTED = 5   /* valid request the library does not implement */
+} fd_status;
+
+/* Arithmetic of the mode products. FD_F64 plans take FP64 vectors; all other
+ * plans take FP32 vectors and keep FP32 intermediates. The 1D eigensolve and
+ * the Lambda^{-1} values are FP64 for every precision.
+ *  FD_BF16 / FD_F16: operands rounded to bf16 / fp16, FP32 MFMA accumulation.
+ *  FD_BF16_SPLIT / FD_F16_SPLIT: both operands split as hi + lo in the
+ *  16-bit type; the products hi*hi + hi*lo + lo*hi are accumulated in FP32. */
+typedef enum {
+  FD_F64 = 0,
+  FD_F32 = 1,
+  FD_BF16 = 2,
+  FD_F16 = 3,
+  FD_BF16_SPLIT = 4,
+  FD_F16_SPLIT = 5
+} fd_precision;
+
+typedef struct fd_plan_s* fd_plan;
+
+/* One unit of work for fd_apply / fd_apply_batched: apply `plan` to `nrhs`
+ * vectors. Vector j starts at r + j*ld (elements) and its result is written
+ * at z + j*ld. ld >= N of the plan. z may alias r exactly (in-place apply);
+ * partially overlapping r and z are not allowed. r and z are FP64 for FD_F64
+ * plans and FP32 otherwise. Between the passes of Algorithm 1 the library
+ * keeps its intermediate tensors in z, so z must not be read by others before
+ * the apply completes. */
+typedef struct {
+  fd_plan plan;
+  const void* r;
+  void* z;
+  int32_t nrhs;
+  int64_t ld;
+} fd_work;
+
+/* ---------------------------------------------------------------- host-only */
+
+/* Univariate factors on a uniform mesh of [0,1] (Sec. 5, the matrices below
+ * eq. prec3D_TH and eq. precQ; weighted pairs of the Appendix):
+ *   [K]_ls = int tau b'_l b'_s,  [M]_ls = int mu b_l b_s,
+ * over the B-splines of `degree` on the open uniform knot vector with n_el
+ * elements and interior knot multiplicity degree - regularity (Sec. 2.1).
+ * dirichlet != 0 drops the first and last function. Quadrature: `npts`
+ * Gauss-Legendre points per element (npts <= 0 selects degree + 1).
+ * tau_q / mu_q: NULL (weight 1) or n_el*npts weights at the quadrature points,
+ * element-major, points in increasing order inside each element.
+ * *n_out receives the matrix order m; K and M (host, caller-allocated, may be
+ * NULL to query m only) receive m*m column-major entries.
+ * Errors: FD_E_ARG for n_el < 1, degree < 1 or > 12, regularity outside
+ * [-1, degree-1], npts > 16, or m < 1 after the boundary condition. */
+fd_status fd_assemble_1d(int32_t n_el, int32_t degree, int32_t regularity, int32_t dirichlet,
+                         int32_t npts, const double* tau_q, const double* mu_q,
+                         int32_t* n_out, double* K, double* M);
+
+/* Gauss-Legendre points and weights on the element mesh used by
+ * fd_assemble_1d: x, w host arrays of n_el*npts (element-major). */
+fd_status fd_quadrature_1d(int32_t n_el, int32_t npts, double* x, double* w);
+
+/* Step 1 of Algorithm 1 for one direction (eq. eig_dec): U (n*n column-major,
+ * columns are eigenvectors) and d (n, ascending) with K U = M U diag(d),
+ * U^T M U = I. K, M: host, n*n column-major, symmetric to 1e-12 relative.
+ * K may be NULL (mass-only: d = 0, U = M^{-1/2} in the Cholesky sense).
+ * Errors: FD_E_ARG (n < 1, NULL M, asymmetry), FD_E_NOTSPD (Cholesky of M
+ * fails). Host computation only; needs no GPU. */
+fd_status fd_factor_1d(int32_t n, const double* K, const double* M, double* U, double* d);
+
+/* ---------------------------------------------------------------- plans */
+
+/* Build a plan for one block (1) with ndim in {2, 3} directions.
+ *  n[i]      : order of the direction-i factors (1 <= n[i] <= 256).
+ *  K[i], M[i]: host FP64, n[i]*n[i] column-major, symmetric; M[i] SPD.
+ *              K == NULL makes a mass-only plan (P = M_d (x) .. (x) M_1,
+ *              Lambda = I, eq. precQ).
+ *  w         : ndim direction weights (NULL = all ones); eq. prec3D_TH uses
+ *              weight 2 on the direction of the velocity component.
+ *  diag_target: NULL, or N = prod(n) host FP64 values, the diagonal of the
+ *              matrix the block stands for (A_kk or Q of Sec. 6); the plan then
+ *              applies z = D^{-1/2} P^{-1} D^{-1/2} r with
+ *              D = diag_target / diag(P). Entries must be > 0.
+ * The factors are computed in FP64 on the host, then packed in the precision
+ * of `prec` and copied to the current HIP device (one copy per plan).
+ * Errors: FD_E_ARG, FD_E_NOTSPD (M not SPD, or Lambda has an entry <= 0, or
+ * a diag_target/diag(P) ratio <= 0), FD_E_NOMEM, FD_E_HIP. */
+fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K,
+                   const double* const* M, const double* w, const double* diag_target,
+                   fd_precision prec, fd_plan* out);
+
+/* Release the plan and its device memory. The caller must make sure no apply
+ * using it is still executing. NULL is accepted. */
+fd_status fd_destroy(fd_plan plan);
+
+/* Plan queries: N = prod(n); device bytes held by the plan. */
+int64_t fd_plan_size(fd_plan plan);
+size_t fd_plan_device_bytes(fd_plan plan);
+
+/* Copy the FP64 factors of direction `dir` back to host arrays (U: n*n
+ * column-major, d: n; either may be NULL). For tests and diagnostics. */
+fd_status fd_plan_factors(fd_plan plan, int32_t dir, double* U, double* d);
+
+/* ---------------------------------------------------------------- apply */
+
+/* z = P^{-1} r (Algorithm 1, steps 2-4) for nrhs vectors of one plan, on
+ * `stream`. Launch errors are returned; there is no host synchronisation. */
+fd_status fd_apply(fd_plan plan, const void* r, void* z, int32_t nrhs, int64_t ld, void* stream);
+
+/* Apply a heterogeneous list of work units (different plans, sizes and
+ * dimensions; all plans of one precision class: FD_F64, or FP32-I/O) as one
+ * set of launches on `stream`: each pass of Algorithm 1 is one launch over the
+ * tiles of every unit. Equivalent to calling fd_apply on each unit. */
+fd_status fd_apply_batched(int32_t count, const fd_work* work, void* stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* fd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FD_H_ */

@@ -1,0 +1,380 @@
+// C ABI of libfd (declared in include/fd.h): plan setup on the host in FP64,
+// device upload of the packed factors, and the pass schedule of Algorithm 1.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fd.h"
+#include "fd_host.h"
+#include "fd_internal.h"
+
+struct fd_plan_s {
+  int ndim = 0;
+  int n[3] = {1, 1, 1};
+  int prec = 0;
+  bool mass_only = false;
+  int64_t N = 0;
+  double w[3] = {1, 1, 1};
+  std::vector<double> U[3], d[3];
+  // device memory (one allocation)
+  void* dev = nullptr;
+  size_t dev_bytes = 0;
+  const void* f_fwd[3] = {nullptr, nullptr, nullptr};  // packed U_i^T
+  const void* f_bwd[3] = {nullptr, nullptr, nullptr};  // packed U_i
+  const double* d_dev[3] = {nullptr, nullptr, nullptr};
+  double lam_w[3] = {1, 1, 1};                          // weights used for Lambda on device
+  const void* scale_dev = nullptr;                      // D^{-1/2}, I/O type
+  int MT[3] = {0, 0, 0}, KS[3] = {0, 0, 0};
+  int device = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+fd_status fail(fd_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+fd_status hip_fail(hipError_t e, const char* what) {
+  return fail(FD_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool io_is_f64(int prec) { return prec == FD_F64; }
+
+// ---- pass schedule
+// 3D: stage 0 mode-1 forward (pre-scale), 1 mode-2 forward, 2 mode-3 forward
+//     + Lambda^{-1} + mode-3 backward, 3 mode-2 backward, 4 mode-1 backward
+//     (post-scale).
+// 2D: stage 0 mode-1 forward, 2 mode-2 fused, 4 mode-1 backward.
+constexpr int kStages = 5;
+
+bool unit_pass(const fd_plan_s* p, const fd_work& wk, int stage, fdk::PassDesc& u) {
+  std::memset(&u, 0, sizeof(u));
+  const int n1 = p->n[0], n2 = p->n[1], n3 = p->n[2];
+  u.in = wk.z;
+  u.out = wk.z;
+  u.ld = wk.ld;
+  u.nrhs = wk.nrhs;
+  u.scale = p->scale_dev;
+  int dir = -1;
+  if (p->ndim == 3) {
+    switch (stage) {
+      case 0: dir = 0; u.A = 1; u.n = n1; u.B = n2 * n3; u.f1 = p->f_fwd[0]; u.in = wk.r;
+              if (p->scale_dev) u.flags |= fdk::kPreScale; break;
+      case 1: dir = 1; u.A = n1; u.n = n2; u.B = n3; u.f1 = p->f_fwd[1]; break;
+      case 2: dir = 2; u.A = n1 * n2; u.n = n3; u.B = 1; u.f1 = p->f_fwd[2]; u.f2 = p->f_bwd[2];
+              u.flags |= fdk::kFuseLambda; break;
+      case 3: dir = 1; u.A = n1; u.n = n2; u.B = n3; u.f1 = p->f_bwd[1]; break;
+      case 4: dir = 0; u.A = 1; u.n = n1; u.B = n2 * n3; u.f1 = p->f_bwd[0];
+              if (p->scale_dev) u.flags |= fdk::kPostScale; break;
+    }
+  } else {
+    switch (stage) {
+      case 0: dir = 0; u.A = 1; u.n = n1; u.B = n2; u.f1 = p->f_fwd[0]; u.in = wk.r;
+              if (p->scale_dev) u.flags |= fdk::kPreScale; break;
+      case 2: dir = 1; u.A = n1; u.n = n2; u.B = 1; u.f1 = p->f_fwd[1]; u.f2 = p->f_bwd[1];
+              u.flags |= fdk::kFuseLambda; break;
+      case 4: dir = 0; u.A = 1; u.n = n1; u.B = n2; u.f1 = p->f_bwd[0];
+              if (p->scale_dev) u.flags |= fdk::kPostScale; break;
+      default: return false;
+    }
+  }
+  u.MT = p->MT[dir];
+  u.KS = p->KS[dir];
+  u.lam_ndim = p->ndim;
+  u.n1 = n1;
+  for (int i = 0; i < 3; ++i) {
+    u.d[i] = p->d_dev[i];
+    u.w[i] = p->lam_w[i];
+  }
+  const int64_t NQ = int64_t(u.A) * u.B;
+  u.tiles_per_rhs = int32_t((NQ + fdk::kTileP - 1) / fdk::kTileP);
+  return true;
+}
+
+fd_status validate_work(const fd_work& wk) {
+  if (!wk.plan) return fail(FD_E_ARG, "fd_apply: NULL plan");
+  if (wk.nrhs < 0) return fail(FD_E_ARG, "fd_apply: nrhs < 0");
+  if (wk.nrhs == 0) return FD_OK;
+  if (!wk.r || !wk.z) return fail(FD_E_ARG, "fd_apply: NULL vector pointer");
+  if (wk.ld < wk.plan->N) return fail(FD_E_ARG, "fd_apply: ld smaller than the plan size");
+  const size_t eb = io_is_f64(wk.plan->prec) ? 8 : 4;
+  const char* r0 = static_cast<const char*>(wk.r);
+  const char* z0 = static_cast<const char*>(wk.z);
+  const size_t span = (size_t(wk.nrhs - 1) * size_t(wk.ld) + size_t(wk.plan->N)) * eb;
+  if (r0 != z0 && r0 < z0 + span && z0 < r0 + span)
+    return fail(FD_E_ARG, "fd_apply: r and z overlap without being equal");
+  return FD_OK;
+}
+
+fd_status run_work(int count, const fd_work* work, hipStream_t stream) {
+  for (int i = 0; i < count; ++i) {
+    fd_status s = validate_work(work[i]);
+    if (s != FD_OK) return s;
+  }
+  const bool f64 = count > 0 && io_is_f64(work[0].plan->prec);
+  for (int i = 0; i < count; ++i)
+    if (io_is_f64(work[i].plan->prec) != f64)
+      return fail(FD_E_ARG, "fd_apply_batched: FP64 and FP32-I/O plans in one call");
+  for (int stage = 0; stage < kStages; ++stage) {
+    for (int prec = 0; prec <= 5; ++prec) {
+      fdk::PassArgs args;
+      args.count = 0;
+      args.total_tiles = 0;
+      int max_mt = 1;
+      auto flush = [&]() -> fd_status {
+        if (args.count == 0) return FD_OK;
+        hipError_t e = fdk::launch_pass(args, prec, max_mt, stream);
+        args.count = 0;
+        args.total_tiles = 0;
+        max_mt = 1;
+        if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        return FD_OK;
+      };
+      for (int i = 0; i < count; ++i) {
+        const fd_work& wk = work[i];
+        if (wk.nrhs == 0 || wk.plan->prec != prec) continue;
+        fdk::PassDesc u;
+        if (!unit_pass(wk.plan, wk, stage, u)) continue;
+        const int64_t tiles = int64_t(u.tiles_per_rhs) * wk.nrhs;
+        if (args.count == fdk::kMaxDesc || int64_t(args.total_tiles) + tiles > 0x7fffffffLL) {
+          fd_status s = flush();
+          if (s != FD_OK) return s;
+        }
+        if (tiles > 0x7fffffffLL) return fail(FD_E_ARG, "fd_apply: too many tiles in one call");
+        u.tile_begin = args.total_tiles;
+        args.u[args.count++] = u;
+        args.total_tiles += int32_t(tiles);
+        max_mt = std::max(max_mt, u.MT);
+      }
+      fd_status s = flush();
+      if (s != FD_OK) return s;
+    }
+  }
+  return FD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fd_last_error(void) { return g_err.c_str(); }
+
+fd_status fd_assemble_1d(int32_t n_el, int32_t degree, int32_t regularity, int32_t dirichlet,
+                         int32_t npts, const double* tau_q, const double* mu_q, int32_t* n_out,
+                         double* K, double* M) {
+  if (!n_out) return fail(FD_E_ARG, "fd_assemble_1d: NULL n_out");
+  int m = 0;
+  if (fdh::assemble_1d(n_el, degree, regularity, dirichlet, npts, tau_q, mu_q, &m, K, M) != 0)
+    return fail(FD_E_ARG, "fd_assemble_1d: invalid n_el/degree/regularity/npts");
+  *n_out = m;
+  return FD_OK;
+}
+
+fd_status fd_quadrature_1d(int32_t n_el, int32_t npts, double* x, double* w) {
+  if (n_el < 1 || npts < 1 || npts > 16 || !x || !w) return fail(FD_E_ARG, "fd_quadrature_1d: bad arguments");
+  fdh::element_quadrature(n_el, npts, x, w);
+  return FD_OK;
+}
+
+fd_status fd_factor_1d(int32_t n, const double* K, const double* M, double* U, double* d) {
+  const char* why = "";
+  const int rc = fdh::factor_1d(n, K, M, U, d, &why);
+  if (rc == 1) return fail(FD_E_ARG, std::string("fd_factor_1d: ") + why);
+  if (rc == 2) return fail(FD_E_NOTSPD, std::string("fd_factor_1d: ") + why);
+  return FD_OK;
+}
+
+fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const double* const* M,
+                   const double* w, const double* diag_target, fd_precision prec, fd_plan* out) {
+  if (!out) return fail(FD_E_ARG, "fd_setup: NULL out");
+  *out = nullptr;
+  if (ndim != 2 && ndim != 3) return fail(FD_E_ARG, "fd_setup: ndim must be 2 or 3");
+  if (!n || !M) return fail(FD_E_ARG, "fd_setup: NULL n or M");
+  if (int(prec) < 0 || int(prec) > 5) return fail(FD_E_ARG, "fd_setup: unknown precision");
+  auto p = new (std::nothrow) fd_plan_s();
+  if (!p) return fail(FD_E_NOMEM, "fd_setup: host allocation");
+  p->ndim = ndim;
+  p->prec = int(prec);
+  p->mass_only = (K == nullptr);
+  p->N = 1;
+  for (int i = 0; i < ndim; ++i) {
+    if (n[i] < 2 || n[i] > fdk::kMaxN) {
+      delete p;
+      return fail(FD_E_ARG, "fd_setup: each n[i] must be in [2, 256]");
+    }
+    if (!M[i] || (K && !K[i])) {
+      delete p;
+      return fail(FD_E_ARG, "fd_setup: NULL factor matrix");
+    }
+    p->n[i] = n[i];
+    p->N *= n[i];
+    p->w[i] = w ? w[i] : 1.0;
+    if (!(p->w[i] > 0.0)) {
+      delete p;
+      return fail(FD_E_ARG, "fd_setup: weights must be > 0");
+    }
+  }
+  // Step 1 of Algorithm 1 in FP64 on the host.
+  for (int i = 0; i < ndim; ++i) {
+    p->U[i].resize(size_t(n[i]) * n[i]);
+    p->d[i].resize(n[i]);
+    const char* why = "";
+    const int rc = fdh::factor_1d(n[i], K ? K[i] : nullptr, M[i], p->U[i].data(), p->d[i].data(), &why);
+    if (rc != 0) {
+      delete p;
+      return fail(rc == 2 ? FD_E_NOTSPD : FD_E_ARG, std::string("fd_setup: direction ") +
+                                                         std::to_string(i + 1) + ": " + why);
+    }
+  }
+  // Lambda must be positive: its smallest entry is sum_i w_i min(d_i).
+  std::vector<double> dl[3];
+  if (p->mass_only) {
+    for (int i = 0; i < ndim; ++i) {
+      dl[i].assign(n[i], i == 0 ? 1.0 : 0.0);
+      p->lam_w[i] = 1.0;
+    }
+  } else {
+    double lmin = 0.0;
+    for (int i = 0; i < ndim; ++i) {
+      lmin += p->w[i] * p->d[i][0];
+      dl[i] = p->d[i];
+      p->lam_w[i] = p->w[i];
+    }
+    if (!(lmin > 0.0)) {
+      delete p;
+      return fail(FD_E_NOTSPD, "fd_setup: the Kronecker-sum eigenvalues are not all positive");
+    }
+  }
+  // Coefficient-aware scaling (Sec. 6): D = target / diag(P), scale = D^{-1/2}.
+  std::vector<double> scale;
+  if (diag_target) {
+    scale.resize(p->N);
+    const int n1 = p->n[0], n2 = p->n[1], n3 = ndim == 3 ? p->n[2] : 1;
+    for (int64_t idx = 0; idx < p->N; ++idx) {
+      const int i1 = int(idx % n1), i2 = int((idx / n1) % n2), i3 = int(idx / (int64_t(n1) * n2));
+      const int ii[3] = {i1, i2, i3};
+      double diagP = 0.0;
+      if (p->mass_only) {
+        diagP = 1.0;
+        for (int k = 0; k < ndim; ++k) diagP *= M[k][ii[k] + size_t(p->n[k]) * ii[k]];
+      } else {
+        for (int k = 0; k < ndim; ++k) {
+          double t = p->w[k] * K[k][ii[k] + size_t(p->n[k]) * ii[k]];
+          for (int l = 0; l < ndim; ++l)
+            if (l != k) t *= M[l][ii[l] + size_t(p->n[l]) * ii[l]];
+          diagP += t;
+        }
+      }
+      const double D = diag_target[idx] / diagP;
+      if (!(D > 0.0) || !std::isfinite(D)) {
+        delete p;
+        return fail(FD_E_NOTSPD, "fd_setup: diag_target / diag(P) must be positive and finite");
+      }
+      scale[idx] = 1.0 / std::sqrt(D);
+    }
+    (void)n3;
+  }
+  // Pack U_i^T (forward) and U_i (backward) in fragment order.
+  const int ks = fdk::mfma_kstep(p->prec);
+  size_t off[3][2], offd[3], offs = 0, total = 0;
+  auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
+  for (int i = 0; i < ndim; ++i) {
+    p->MT[i] = (n[i] + 15) / 16;
+    p->KS[i] = (n[i] + ks - 1) / ks;
+    const size_t pb = fdk::packed_bytes(n[i], p->prec);
+    off[i][0] = total; total = align(total + pb);
+    off[i][1] = total; total = align(total + pb);
+    offd[i] = total; total = align(total + sizeof(double) * n[i]);
+  }
+  const size_t eb = io_is_f64(p->prec) ? 8 : 4;
+  if (diag_target) { offs = total; total = align(total + eb * size_t(p->N)); }
+  std::vector<unsigned char> host(total, 0);
+  std::vector<double> Ft;
+  for (int i = 0; i < ndim; ++i) {
+    const int m = n[i];
+    Ft.assign(size_t(m) * m, 0.0);
+    for (int r = 0; r < m; ++r)
+      for (int c = 0; c < m; ++c) Ft[r + size_t(m) * c] = p->U[i][c + size_t(m) * r];
+    fdk::pack_factor(m, Ft.data(), p->prec, host.data() + off[i][0]);
+    fdk::pack_factor(m, p->U[i].data(), p->prec, host.data() + off[i][1]);
+    std::memcpy(host.data() + offd[i], dl[i].data(), sizeof(double) * m);
+  }
+  if (diag_target) {
+    if (eb == 8) std::memcpy(host.data() + offs, scale.data(), 8 * size_t(p->N));
+    else
+      for (int64_t k = 0; k < p->N; ++k) reinterpret_cast<float*>(host.data() + offs)[k] = float(scale[k]);
+  }
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) { delete p; return hip_fail(e, "hipGetDevice"); }
+  e = hipMalloc(&p->dev, total);
+  if (e != hipSuccess) {
+    delete p;
+    return e == hipErrorOutOfMemory ? fail(FD_E_NOMEM, "fd_setup: device allocation") : hip_fail(e, "hipMalloc");
+  }
+  e = hipMemcpy(p->dev, host.data(), total, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(p->dev);
+    delete p;
+    return hip_fail(e, "hipMemcpy");
+  }
+  p->dev_bytes = total;
+  unsigned char* base = static_cast<unsigned char*>(p->dev);
+  for (int i = 0; i < ndim; ++i) {
+    p->f_fwd[i] = base + off[i][0];
+    p->f_bwd[i] = base + off[i][1];
+    p->d_dev[i] = reinterpret_cast<const double*>(base + offd[i]);
+  }
+  if (diag_target) p->scale_dev = base + offs;
+  *out = p;
+  return FD_OK;
+}
+
+fd_status fd_destroy(fd_plan plan) {
+  if (!plan) return FD_OK;
+  if (plan->dev) {
+    hipError_t e = hipFree(plan->dev);
+    plan->dev = nullptr;
+    delete plan;
+    if (e != hipSuccess) return hip_fail(e, "hipFree");
+    return FD_OK;
+  }
+  delete plan;
+  return FD_OK;
+}
+
+int64_t fd_plan_size(fd_plan plan) { return plan ? plan->N : 0; }
+
+size_t fd_plan_device_bytes(fd_plan plan) { return plan ? plan->dev_bytes : 0; }
+
+fd_status fd_plan_factors(fd_plan plan, int32_t dir, double* U, double* d) {
+  if (!plan || dir < 0 || dir >= plan->ndim) return fail(FD_E_ARG, "fd_plan_factors: bad plan or direction");
+  const int m = plan->n[dir];
+  if (U) std::memcpy(U, plan->U[dir].data(), sizeof(double) * m * m);
+  if (d) std::memcpy(d, plan->d[dir].data(), sizeof(double) * m);
+  return FD_OK;
+}
+
+fd_status fd_apply(fd_plan plan, const void* r, void* z, int32_t nrhs, int64_t ld, void* stream) {
+  fd_work wk;
+  wk.plan = plan;
+  wk.r = r;
+  wk.z = z;
+  wk.nrhs = nrhs;
+  wk.ld = ld;
+  return run_work(1, &wk, static_cast<hipStream_t>(stream));
+}
+
+fd_status fd_apply_batched(int32_t count, const fd_work* work, void* stream) {
+  if (count < 0 || (count > 0 && !work)) return fail(FD_E_ARG, "fd_apply_batched: bad count/work");
+  return run_work(count, work, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,211 @@
+"""ctypes binding of libfd (C ABI in include/fd.h).
+
+Argument marshalling only: every arithmetic step of the apply runs in the HIP
+library. Device buffers and streams come from torch (tensors and
+``torch.cuda.Stream``); host matrices are numpy FP64 arrays. The library must
+be built (``python -m paper_1712_00403_amd.build``); loading fails loudly
+otherwise, there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfd.so")
+
+FD_OK, FD_E_ARG, FD_E_NOTSPD, FD_E_NOMEM, FD_E_HIP, FD_E_UNSUPPORTED = range(6)
+PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "bf16_split": 4, "f16_split": 5}
+STATUS_NAMES = {0: "FD_OK", 1: "FD_E_ARG", 2: "FD_E_NOTSPD", 3: "FD_E_NOMEM", 4: "FD_E_HIP",
+                5: "FD_E_UNSUPPORTED"}
+
+# every symbol declared in include/fd.h
+EXPORTS = ("fd_assemble_1d", "fd_quadrature_1d", "fd_factor_1d", "fd_setup", "fd_destroy",
+           "fd_plan_size", "fd_plan_device_bytes", "fd_plan_factors", "fd_apply",
+           "fd_apply_batched", "fd_last_error")
+
+
+class FDError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class FDWork(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("r", ctypes.c_void_p), ("z", ctypes.c_void_p),
+                ("nrhs", ctypes.c_int32), ("ld", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libfd.so (once). Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libfd.so not found at {LIB_PATH}; build it with "
+                           "`python -m paper_1712_00403_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    c_dp = ctypes.POINTER(ctypes.c_double)
+    L.fd_last_error.restype = ctypes.c_char_p
+    L.fd_assemble_1d.argtypes = [ctypes.c_int32] * 5 + [c_dp, c_dp, ctypes.POINTER(ctypes.c_int32), c_dp, c_dp]
+    L.fd_quadrature_1d.argtypes = [ctypes.c_int32, ctypes.c_int32, c_dp, c_dp]
+    L.fd_factor_1d.argtypes = [ctypes.c_int32, c_dp, c_dp, c_dp, c_dp]
+    L.fd_setup.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(c_dp),
+                           ctypes.POINTER(c_dp), c_dp, c_dp, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]
+    L.fd_destroy.argtypes = [ctypes.c_void_p]
+    L.fd_plan_size.argtypes = [ctypes.c_void_p]
+    L.fd_plan_size.restype = ctypes.c_int64
+    L.fd_plan_device_bytes.argtypes = [ctypes.c_void_p]
+    L.fd_plan_device_bytes.restype = ctypes.c_size_t
+    L.fd_plan_factors.argtypes = [ctypes.c_void_p, ctypes.c_int32, c_dp, c_dp]
+    L.fd_apply.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                           ctypes.c_int64, ctypes.c_void_p]
+    L.fd_apply_batched.argtypes = [ctypes.c_int32, ctypes.POINTER(FDWork), ctypes.c_void_p]
+    for name in ("fd_assemble_1d", "fd_quadrature_1d", "fd_factor_1d", "fd_setup", "fd_destroy",
+                 "fd_plan_factors", "fd_apply", "fd_apply_batched"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != FD_OK:
+        raise FDError(status, lib().fd_last_error().decode())
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if a is not None else None
+
+
+def _f64c(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+# ---------------------------------------------------------------- host-only calls
+
+def assemble_1d(n_el, degree, regularity, dirichlet, npts=0, tau=None, mu=None):
+    """Univariate (K, M), column-major FP64 (see fd_assemble_1d)."""
+    L = lib()
+    m = ctypes.c_int32(0)
+    tq = None if tau is None else _f64c(tau).ravel()
+    mq = None if mu is None else _f64c(mu).ravel()
+    _check(L.fd_assemble_1d(n_el, degree, regularity, int(bool(dirichlet)), npts, _dp(tq), _dp(mq),
+                            ctypes.byref(m), None, None))
+    K = np.zeros((m.value, m.value), order="F")
+    M = np.zeros((m.value, m.value), order="F")
+    _check(L.fd_assemble_1d(n_el, degree, regularity, int(bool(dirichlet)), npts, _dp(tq), _dp(mq),
+                            ctypes.byref(m), K.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                            M.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return np.ascontiguousarray(K), np.ascontiguousarray(M)
+
+
+def quadrature_1d(n_el, npts):
+    x = np.zeros(n_el * npts)
+    w = np.zeros(n_el * npts)
+    _check(lib().fd_quadrature_1d(n_el, npts, _dp(x), _dp(w)))
+    return x.reshape(n_el, npts), w.reshape(n_el, npts)
+
+
+def factor_1d(K, M):
+    """(U, d) of the pencil (K, M) computed by the library on the host."""
+    M = _f64c(M)
+    n = M.shape[0]
+    Kc = None if K is None else np.asfortranarray(np.asarray(K, dtype=np.float64))
+    Mc = np.asfortranarray(M)
+    U = np.zeros((n, n), order="F")
+    d = np.zeros(n)
+    _check(lib().fd_factor_1d(n, None if Kc is None else Kc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              Mc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              U.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _dp(d)))
+    return np.ascontiguousarray(U), d
+
+
+# ---------------------------------------------------------------- plans
+
+class Plan:
+    """One Kronecker-sum block on the device (fd_setup / fd_destroy)."""
+
+    def __init__(self, Ks, Ms, weights=None, diag_target=None, precision="f64"):
+        L = lib()
+        ndim = len(Ms)
+        self.ndim = ndim
+        self.n = tuple(int(np.asarray(M).shape[0]) for M in Ms)
+        self.precision = precision
+        self.prec_id = PRECISIONS[precision]
+        self.io_dtype = "float64" if precision == "f64" else "float32"
+        c_dp = ctypes.POINTER(ctypes.c_double)
+        self._Ms = [np.asfortranarray(np.asarray(M, dtype=np.float64)) for M in Ms]
+        self._Ks = None if Ks is None else [np.asfortranarray(np.asarray(K, dtype=np.float64)) for K in Ks]
+        Marr = (c_dp * ndim)(*[M.ctypes.data_as(c_dp) for M in self._Ms])
+        Karr = None if self._Ks is None else (c_dp * ndim)(*[K.ctypes.data_as(c_dp) for K in self._Ks])
+        narr = (ctypes.c_int32 * ndim)(*self.n)
+        w = None if weights is None else _f64c(weights)
+        dt = None if diag_target is None else _f64c(diag_target).ravel()
+        h = ctypes.c_void_p(0)
+        _check(L.fd_setup(ndim, narr, Karr, Marr, _dp(w), _dp(dt), self.prec_id, ctypes.byref(h)))
+        self.handle = h.value
+        self.N = int(L.fd_plan_size(self.handle))
+        self.device_bytes = int(L.fd_plan_device_bytes(self.handle))
+
+    def factors(self, direction):
+        n = self.n[direction]
+        U = np.zeros((n, n), order="F")
+        d = np.zeros(n)
+        _check(lib().fd_plan_factors(self.handle, direction,
+                                     U.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _dp(d)))
+        return np.ascontiguousarray(U), d
+
+    def apply_ptr(self, r_ptr, z_ptr, nrhs, ld, stream=0):
+        _check(lib().fd_apply(self.handle, r_ptr, z_ptr, int(nrhs), int(ld), stream))
+
+    def apply(self, r, z=None, stream=None):
+        """z = P^{-1} r for a torch device tensor r of shape (nrhs, N) or (N,)."""
+        import torch
+        if r.dtype != getattr(torch, self.io_dtype):
+            raise TypeError(f"plan expects {self.io_dtype} vectors")
+        if z is None:
+            z = torch.empty_like(r)
+        r2 = r.reshape(-1, r.shape[-1])
+        if r2.shape[-1] < self.N or r.stride(-1) != 1:
+            raise ValueError("vectors must be contiguous with at least N entries")
+        nrhs = r2.shape[0]
+        ld = r2.stride(0) if nrhs > 1 else r2.shape[-1]
+        s = _stream_handle(stream)
+        self.apply_ptr(r.data_ptr(), z.data_ptr(), nrhs, ld, s)
+        return z
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().fd_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def apply_batched(works, stream=None):
+    """works: iterable of (plan, r_ptr, z_ptr, nrhs, ld) -> one fd_apply_batched call."""
+    works = list(works)
+    arr = (FDWork * len(works))()
+    for i, (plan, r, z, nrhs, ld) in enumerate(works):
+        arr[i].plan = plan.handle
+        arr[i].r = r
+        arr[i].z = z
+        arr[i].nrhs = nrhs
+        arr[i].ld = ld
+    _check(lib().fd_apply_batched(len(works), arr, _stream_handle(stream)))

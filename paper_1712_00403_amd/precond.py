@@ -1,0 +1,66 @@
+"""Block-diagonal Stokes preconditioner P_D = diag(P_V,1, .., P_V,d, P_Q) on the device.
+
+P_D of eq. P_D (Sec. 4) with the simple blocks of Sec. 5 (eq. prec3D_TH,
+eq. precQ): each velocity block is a Kronecker sum applied by FD, the pressure
+block a Kronecker product of mass matrices applied by FD with Lambda = I. The
+univariate factors come from the library's own assembly (fd_assemble_1d); the
+apply of all blocks of all residuals is one fd_apply_batched call.
+
+Block vectors are [u_1; ..; u_d; p] with the velocity components first, as in
+the Stokes matrix of Sec. 3; a batch of residuals is residual-major.
+"""
+import numpy as np
+
+from . import fd
+
+
+def block_factors(spec):
+    """(Ks, Ms) of one block from the library's assembly (Ks None for mass-only)."""
+    Ks, Ms = [], []
+    for f in spec.dirs:
+        K, M = fd.assemble_1d(f.n_el, f.degree, f.regularity, f.dirichlet)
+        Ks.append(K)
+        Ms.append(M)
+    return (None if spec.mass_only else Ks), Ms
+
+
+class BlockPreconditioner:
+    """Plans for every block of a workloads.Problem, sharing 1D factors per block."""
+
+    def __init__(self, problem, precision="f64", diag_targets=None, factors=None):
+        self.problem = problem
+        self.precision = precision
+        self.plans = []
+        self.sizes = []
+        for bi, spec in enumerate(problem.blocks):
+            Ks, Ms = factors[bi] if factors is not None else block_factors(spec)
+            dt = None if diag_targets is None else diag_targets[bi]
+            plan = fd.Plan(Ks, Ms, weights=np.asarray(spec.weights), diag_target=dt, precision=precision)
+            self.plans.append(plan)
+            self.sizes.append(plan.N)
+        self.offsets = np.concatenate([[0], np.cumsum(self.sizes)]).astype(np.int64)
+        self.N = int(self.offsets[-1])
+        self.io_dtype = self.plans[0].io_dtype
+
+    def works(self, r_ptr, z_ptr, nrhs, ld=None, elem_bytes=None):
+        ld = self.N if ld is None else ld
+        eb = elem_bytes or (8 if self.io_dtype == "float64" else 4)
+        return [(p, r_ptr + int(o) * eb, z_ptr + int(o) * eb, nrhs, ld)
+                for p, o in zip(self.plans, self.offsets[:-1])]
+
+    def apply(self, r, z=None, stream=None):
+        """z = P_D^{-1} r for a torch device tensor of shape (nrhs, N_block) or (N_block,)."""
+        import torch
+        if r.dtype != getattr(torch, self.io_dtype):
+            raise TypeError(f"preconditioner expects {self.io_dtype} vectors")
+        if z is None:
+            z = torch.empty_like(r)
+        r2 = r.reshape(-1, r.shape[-1])
+        if r2.shape[-1] != self.N or not r.is_contiguous() or not z.is_contiguous():
+            raise ValueError("block vectors must be contiguous with N_block entries")
+        fd.apply_batched(self.works(r.data_ptr(), z.data_ptr(), r2.shape[0]), stream)
+        return z
+
+    def close(self):
+        for p in self.plans:
+            p.close()

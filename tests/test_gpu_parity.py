@@ -1,0 +1,201 @@
+"""GPU parity: the HIP FD apply against the FP64 oracle, element by element.
+
+Each case prints its name before touching the GPU. Relative errors are per
+residual and per block (the pressure block's entries are orders of magnitude
+larger than the velocity ones, so one norm over the whole block vector would
+hide velocity errors).
+"""
+import numpy as np
+import pytest
+
+from oracle.assemble import pressure_1d, taylor_hood_velocity_1d
+from oracle.fd import FDFactors, block_apply, fd_apply, mass_solve_banded, velocity_weights
+from paper_1712_00403_amd import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+# per-precision tolerance on ||z - z_oracle|| / ||z_oracle||
+TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-2, "bf16_split": 1e-4, "f16": 5e-3, "f16_split": 1e-4}
+
+
+def _fd():
+    from paper_1712_00403_amd import fd
+    return fd
+
+
+def _case(msg):
+    print(f"[gpu case] {msg}", flush=True)
+
+
+def _vel_factors(n_el, p):
+    vel = [taylor_hood_velocity_1d(n, p) for n in n_el]
+    return [v[0] for v in vel], [v[1] for v in vel]
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _run_plan(plan, r, inplace=False, ld=None):
+    """Apply plan to host residuals r (nrhs, N) through device tensors; returns host z."""
+    dt = torch.float64 if plan.io_dtype == "float64" else torch.float32
+    nrhs, N = r.shape
+    ld = N if ld is None else ld
+    buf = torch.zeros((nrhs, ld), dtype=dt, device="cuda")
+    buf[:, :N] = torch.from_numpy(r).to(dt).cuda()
+    out = buf if inplace else torch.full_like(buf, float("nan"))
+    plan.apply_ptr(buf.data_ptr(), out.data_ptr(), nrhs, ld, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy()
+    if not inplace and ld > N:
+        assert np.all(np.isnan(res[:, N:])), "apply wrote outside the vectors"
+    return res[:, :N].astype(np.float64)
+
+
+CASES_3D = [((3, 4, 5), 2, (2.0, 1.0, 1.0)), ((18, 10, 22), 3, (1.0, 2.0, 1.0)),
+            ((8, 33, 5), 1, (1.0, 1.0, 2.0)), ((6, 7, 9), 5, (1.0, 1.0, 1.0))]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "bf16_split"])
+@pytest.mark.parametrize("n_el,p,w", CASES_3D)
+def test_fd3d_velocity_block(prec, n_el, p, w):
+    _case(f"fd3d velocity n_el={n_el} p={p} w={w} prec={prec}")
+    Ks, Ms = _vel_factors(n_el, p)
+    f = FDFactors(Ks, Ms, np.array(w))
+    plan = _fd().Plan(Ks, Ms, weights=np.array(w), precision=prec)
+    r = workloads.residuals(11, 3, plan.N)
+    z = _run_plan(plan, r)
+    for j in range(r.shape[0]):
+        err = _rel(z[j], fd_apply(f, r[j]))
+        assert err < TOL[prec], f"residual {j}: rel err {err:.3e}"
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "bf16_split"])
+@pytest.mark.parametrize("n_el,p", [((16, 16), 2), ((13, 29), 3), ((2, 3), 1), ((60, 40), 4)])
+def test_fd2d_velocity_block(prec, n_el, p):
+    _case(f"fd2d velocity n_el={n_el} p={p} prec={prec}")
+    Ks, Ms = _vel_factors(n_el, p)
+    f = FDFactors(Ks, Ms)
+    plan = _fd().Plan(Ks, Ms, precision=prec)
+    r = workloads.residuals(12, 4, plan.N)
+    z = _run_plan(plan, r)
+    for j in range(r.shape[0]):
+        err = _rel(z[j], fd_apply(f, r[j]))
+        assert err < TOL[prec], f"residual {j}: rel err {err:.3e}"
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("n_el,p", [((5, 9, 4), 2), ((20, 11, 17), 3), ((7, 12), 2)])
+def test_pressure_mass_block(prec, n_el, p):
+    _case(f"pressure mass n_el={n_el} p={p} prec={prec}")
+    Ms = [pressure_1d(n, p) for n in n_el]
+    plan = _fd().Plan(None, Ms, precision=prec)
+    r = workloads.residuals(13, 2, plan.N)
+    z = _run_plan(plan, r)
+    for j in range(r.shape[0]):
+        err = _rel(z[j], mass_solve_banded(Ms, r[j]))
+        assert err < TOL[prec], f"residual {j}: rel err {err:.3e}"
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_inplace_and_strided(prec):
+    _case(f"in-place and ld > N, prec={prec}")
+    Ks, Ms = _vel_factors((9, 6, 11), 2)
+    f = FDFactors(Ks, Ms)
+    plan = _fd().Plan(Ks, Ms, precision=prec)
+    r = workloads.residuals(14, 3, plan.N)
+    for inplace in (True, False):
+        z = _run_plan(plan, r, inplace=inplace, ld=plan.N + 37)
+        for j in range(3):
+            assert _rel(z[j], fd_apply(f, r[j])) < TOL[prec]
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_scaled_variant(prec):
+    _case(f"diagonal scaling, prec={prec}")
+    Ks, Ms = _vel_factors((5, 7, 6), 3)
+    f = FDFactors(Ks, Ms, np.array([1.0, 1.0, 2.0]))
+    rng = np.random.default_rng(21)
+    N = int(np.prod(f.n))
+    # diag(P) computed from the 1D diagonals, target = diag(P) * D
+    dK = [np.diag(K) for K in Ks]
+    dM = [np.diag(M) for M in Ms]
+    diagP = (2.0 * np.einsum("k,j,i->kji", dK[2], dM[1], dM[0]) + np.einsum("k,j,i->kji", dM[2], dK[1], dM[0])
+             + np.einsum("k,j,i->kji", dM[2], dM[1], dK[0])).reshape(-1)
+    D = 0.5 + rng.random(N)
+    plan = _fd().Plan(Ks, Ms, weights=np.array([1.0, 1.0, 2.0]), diag_target=diagP * D, precision=prec)
+    r = workloads.residuals(15, 2, plan.N)
+    z = _run_plan(plan, r)
+    s = 1.0 / np.sqrt(D)
+    for j in range(2):
+        zo = s * fd_apply(f, s * r[j])
+        assert _rel(z[j], zo) < TOL[prec]
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_block_preconditioner_mixed_batch(prec):
+    """2D and 3D problems, velocity and pressure blocks, in one fd_apply_batched call."""
+    _case(f"batched heterogeneous block preconditioners, prec={prec}")
+    from paper_1712_00403_amd.precond import BlockPreconditioner
+    fd = _fd()
+    probs = [workloads.taylor_hood_problem((4, 6, 5), 2), workloads.taylor_hood_problem((10, 7), 3),
+             workloads.taylor_hood_problem((3, 3, 8), 4)]
+    pcs = [BlockPreconditioner(pr, precision=prec) for pr in probs]
+    dt = torch.float64 if prec == "f64" else torch.float32
+    rs, zs, works = [], [], []
+    for i, pc in enumerate(pcs):
+        r = workloads.residuals(30 + i, 2, pc.N)
+        rt = torch.from_numpy(r).to(dt).cuda()
+        zt = torch.empty_like(rt)
+        rs.append(r)
+        zs.append((rt, zt))
+        works += pc.works(rt.data_ptr(), zt.data_ptr(), 2)
+    fd.apply_batched(works)
+    torch.cuda.synchronize()
+    for pr, pc, r, (rt, zt) in zip(probs, pcs, rs, zs):
+        z = zt.cpu().numpy().astype(np.float64)
+        d, p = pr.ndim, pr.p
+        Ks, Ms = _vel_factors(pr.n_el, p)
+        wts = [np.array(b.weights) for b in pr.blocks[:d]]
+        facs = [FDFactors(Ks, Ms, wts[k]) for k in range(d)]
+        Mp = [pressure_1d(n, p) for n in pr.n_el]
+        for j in range(2):
+            zo = block_apply(facs, Mp, r[j])
+            for a, b in zip(pc.offsets[:-1], pc.offsets[1:]):
+                assert _rel(z[j, a:b], zo[a:b]) < TOL[prec]
+        pc.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_full_size_64cube_p3(prec):
+    """The 64^3, p = 3 block (n_V = 129, n_Q = 67) in the launch configuration of the bench."""
+    _case(f"full-size 64^3 p=3 block, prec={prec}")
+    from paper_1712_00403_amd.precond import BlockPreconditioner
+    prob = workloads.CONFIGS["c2_3d_64_p3"]["problem"]()
+    pc = BlockPreconditioner(prob, precision=prec)
+    assert pc.sizes == [129 ** 3] * 3 + [67 ** 3]
+    nrhs = 2
+    r = workloads.residuals(1, nrhs, pc.N)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    z = pc.apply(torch.from_numpy(r).to(dt).cuda())
+    torch.cuda.synchronize()
+    z = z.cpu().numpy().astype(np.float64)
+    Ks, Ms = _vel_factors(prob.n_el, 3)
+    Mp = [pressure_1d(n, 3) for n in prob.n_el]
+    for k in range(4):
+        a, b = pc.offsets[k], pc.offsets[k + 1]
+        if k < 3:
+            f = FDFactors(Ks, Ms, velocity_weights(3, k))
+            zo = fd_apply(f, r[0, a:b])
+        else:
+            zo = mass_solve_banded(Mp, r[0, a:b])
+        err = _rel(z[0, a:b], zo)
+        print(f"  block {k}: rel err {err:.3e}")
+        assert err < TOL[prec]
+    pc.close()
