@@ -158,6 +158,20 @@ fd_status fd_apply(fd_plan plan, const void* r, void* z, int32_t nrhs, int64_t l
  * tiles of every unit. Equivalent to calling fd_apply on each unit. */
 fd_status fd_apply_batched(int32_t count, const fd_work* work, void* stream);
 
+/* ---------------------------------------------------------------- diagnostics */
+
+/* Per-stage kernel timing. While enabled, the launches of each stage of
+ * fd_apply / fd_apply_batched are bracketed by two HIP events recorded on the
+ * stream the kernels run on. Stages: 0 mode-1 forward, 1 mode-2 forward,
+ * 2 last-mode forward + Lambda^{-1} + last-mode backward, 3 mode-2 backward,
+ * 4 mode-1 backward (2D plans use stages 0, 2, 4). fd_timing_read waits for
+ * the recorded events, adds the milliseconds of each stage into ms[0..4] and
+ * the number of bracketed stage executions into count[0..4] (both host arrays
+ * of 5, overwritten), and clears the record. Not for concurrent use from
+ * several host threads. */
+fd_status fd_timing_enable(int32_t enable);
+fd_status fd_timing_read(double* ms, int32_t* count);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* fd_last_error(void);
 

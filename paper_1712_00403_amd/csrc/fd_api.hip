@@ -37,6 +37,13 @@ namespace {
 
 thread_local std::string g_err;
 
+struct StageRecord {
+  int stage;
+  hipEvent_t start, end;
+};
+bool g_timing = false;
+std::vector<StageRecord> g_records;
+
 fd_status fail(fd_status s, const std::string& msg) {
   g_err = msg;
   return s;
@@ -124,6 +131,20 @@ fd_status run_work(int count, const fd_work* work, hipStream_t stream) {
     if (io_is_f64(work[i].plan->prec) != f64)
       return fail(FD_E_ARG, "fd_apply_batched: FP64 and FP32-I/O plans in one call");
   for (int stage = 0; stage < kStages; ++stage) {
+    StageRecord rec{stage, nullptr, nullptr};
+    if (g_timing) {
+      bool any = false;
+      for (int i = 0; i < count; ++i) {
+        fdk::PassDesc probe;
+        if (work[i].nrhs > 0 && unit_pass(work[i].plan, work[i], stage, probe)) any = true;
+      }
+      if (any) {
+        hipError_t e = hipEventCreate(&rec.start);
+        if (e == hipSuccess) e = hipEventCreate(&rec.end);
+        if (e == hipSuccess) e = hipEventRecord(rec.start, stream);
+        if (e != hipSuccess) return hip_fail(e, "timing event");
+      }
+    }
     for (int prec = 0; prec <= 5; ++prec) {
       fdk::PassArgs args;
       args.count = 0;
@@ -157,6 +178,11 @@ fd_status run_work(int count, const fd_work* work, hipStream_t stream) {
       fd_status s = flush();
       if (s != FD_OK) return s;
     }
+    if (rec.start) {
+      hipError_t e = hipEventRecord(rec.end, stream);
+      if (e != hipSuccess) return hip_fail(e, "timing event");
+      g_records.push_back(rec);
+    }
   }
   return FD_OK;
 }
@@ -166,6 +192,32 @@ fd_status run_work(int count, const fd_work* work, hipStream_t stream) {
 extern "C" {
 
 const char* fd_last_error(void) { return g_err.c_str(); }
+
+fd_status fd_timing_enable(int32_t enable) {
+  g_timing = enable != 0;
+  return FD_OK;
+}
+
+fd_status fd_timing_read(double* ms, int32_t* count) {
+  if (!ms || !count) return fail(FD_E_ARG, "fd_timing_read: NULL output");
+  for (int s = 0; s < kStages; ++s) {
+    ms[s] = 0.0;
+    count[s] = 0;
+  }
+  fd_status st = FD_OK;
+  for (auto& r : g_records) {
+    float t = 0.0f;
+    hipError_t e = hipEventSynchronize(r.end);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, r.start, r.end);
+    if (e != hipSuccess && st == FD_OK) st = hip_fail(e, "fd_timing_read");
+    ms[r.stage] += t;
+    count[r.stage] += 1;
+    (void)hipEventDestroy(r.start);
+    (void)hipEventDestroy(r.end);
+  }
+  g_records.clear();
+  return st;
+}
 
 fd_status fd_assemble_1d(int32_t n_el, int32_t degree, int32_t regularity, int32_t dirichlet,
                          int32_t npts, const double* tau_q, const double* mu_q, int32_t* n_out,

@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "FD_OK", 1: "FD_E_ARG", 2: "FD_E_NOTSPD", 3: "FD_E_NOMEM", 4:
 # every symbol declared in include/fd.h
 EXPORTS = ("fd_assemble_1d", "fd_quadrature_1d", "fd_factor_1d", "fd_setup", "fd_destroy",
            "fd_plan_size", "fd_plan_device_bytes", "fd_plan_factors", "fd_apply",
-           "fd_apply_batched", "fd_last_error")
+           "fd_apply_batched", "fd_timing_enable", "fd_timing_read", "fd_last_error")
 
 
 class FDError(RuntimeError):
@@ -64,7 +64,9 @@ def lib():
     L.fd_apply.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                            ctypes.c_int64, ctypes.c_void_p]
     L.fd_apply_batched.argtypes = [ctypes.c_int32, ctypes.POINTER(FDWork), ctypes.c_void_p]
-    for name in ("fd_assemble_1d", "fd_quadrature_1d", "fd_factor_1d", "fd_setup", "fd_destroy",
+    L.fd_timing_enable.argtypes = [ctypes.c_int32]
+    L.fd_timing_read.argtypes = [c_dp, ctypes.POINTER(ctypes.c_int32)]
+    for name in ("fd_timing_enable", "fd_timing_read", "fd_assemble_1d", "fd_quadrature_1d", "fd_factor_1d", "fd_setup", "fd_destroy",
                  "fd_plan_factors", "fd_apply", "fd_apply_batched"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -209,3 +211,18 @@ def apply_batched(works, stream=None):
         arr[i].nrhs = nrhs
         arr[i].ld = ld
     _check(lib().fd_apply_batched(len(works), arr, _stream_handle(stream)))
+
+
+STAGE_NAMES = ("mode1_fwd", "mode2_fwd", "last_mode_fused", "mode2_bwd", "mode1_bwd")
+
+
+def timing_enable(on=True):
+    _check(lib().fd_timing_enable(1 if on else 0))
+
+
+def timing_read():
+    """{stage name: (total ms, executions)} since the last read (waits for the events)."""
+    ms = (ctypes.c_double * 5)()
+    cnt = (ctypes.c_int32 * 5)()
+    _check(lib().fd_timing_read(ms, cnt))
+    return {STAGE_NAMES[i]: (ms[i], cnt[i]) for i in range(5)}
