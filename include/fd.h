@@ -116,7 +116,8 @@ fd_status fd_factor_1d(int32_t n, const double* K, const double* M, double* U, d
 /* ---------------------------------------------------------------- plans */
 
 /* Build a plan for one block (1) with ndim in {2, 3} directions.
- *  n[i]      : order of the direction-i factors (1 <= n[i] <= 256).
+ *  n[i]      : order of the direction-i factors (2 <= n[i] <= 256), with
+ *              N = prod(n) < 2^28.
  *  K[i], M[i]: host FP64, n[i]*n[i] column-major, symmetric; M[i] SPD.
  *              K == NULL makes a mass-only plan (P = M_d (x) .. (x) M_1,
  *              Lambda = I, eq. precQ).

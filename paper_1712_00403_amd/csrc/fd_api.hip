@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -26,6 +27,8 @@ struct fd_plan_s {
   size_t dev_bytes = 0;
   const void* f_fwd[3] = {nullptr, nullptr, nullptr};  // packed U_i^T
   const void* f_bwd[3] = {nullptr, nullptr, nullptr};  // packed U_i
+  const void* p_fwd[3] = {nullptr, nullptr, nullptr};  // plain row-major U_i^T
+  const void* p_bwd[3] = {nullptr, nullptr, nullptr};  // plain row-major U_i
   const double* d_dev[3] = {nullptr, nullptr, nullptr};
   double lam_w[3] = {1, 1, 1};                          // weights used for Lambda on device
   const void* scale_dev = nullptr;                      // D^{-1/2}, I/O type
@@ -71,27 +74,36 @@ bool unit_pass(const fd_plan_s* p, const fd_work& wk, int stage, fdk::PassDesc& 
   u.nrhs = wk.nrhs;
   u.scale = p->scale_dev;
   int dir = -1;
+  bool fwd = false, fused = false;
   if (p->ndim == 3) {
     switch (stage) {
-      case 0: dir = 0; u.A = 1; u.n = n1; u.B = n2 * n3; u.f1 = p->f_fwd[0]; u.in = wk.r;
+      case 0: dir = 0; u.A = 1; u.n = n1; u.B = n2 * n3; u.in = wk.r; fwd = true;
               if (p->scale_dev) u.flags |= fdk::kPreScale; break;
-      case 1: dir = 1; u.A = n1; u.n = n2; u.B = n3; u.f1 = p->f_fwd[1]; break;
-      case 2: dir = 2; u.A = n1 * n2; u.n = n3; u.B = 1; u.f1 = p->f_fwd[2]; u.f2 = p->f_bwd[2];
-              u.flags |= fdk::kFuseLambda; break;
-      case 3: dir = 1; u.A = n1; u.n = n2; u.B = n3; u.f1 = p->f_bwd[1]; break;
-      case 4: dir = 0; u.A = 1; u.n = n1; u.B = n2 * n3; u.f1 = p->f_bwd[0];
+      case 1: dir = 1; u.A = n1; u.n = n2; u.B = n3; fwd = true; break;
+      case 2: dir = 2; u.A = n1 * n2; u.n = n3; u.B = 1; fused = true; break;
+      case 3: dir = 1; u.A = n1; u.n = n2; u.B = n3; break;
+      case 4: dir = 0; u.A = 1; u.n = n1; u.B = n2 * n3;
               if (p->scale_dev) u.flags |= fdk::kPostScale; break;
     }
   } else {
     switch (stage) {
-      case 0: dir = 0; u.A = 1; u.n = n1; u.B = n2; u.f1 = p->f_fwd[0]; u.in = wk.r;
+      case 0: dir = 0; u.A = 1; u.n = n1; u.B = n2; u.in = wk.r; fwd = true;
               if (p->scale_dev) u.flags |= fdk::kPreScale; break;
-      case 2: dir = 1; u.A = n1; u.n = n2; u.B = 1; u.f1 = p->f_fwd[1]; u.f2 = p->f_bwd[1];
-              u.flags |= fdk::kFuseLambda; break;
-      case 4: dir = 0; u.A = 1; u.n = n1; u.B = n2; u.f1 = p->f_bwd[0];
+      case 2: dir = 1; u.A = n1; u.n = n2; u.B = 1; fused = true; break;
+      case 4: dir = 0; u.A = 1; u.n = n1; u.B = n2;
               if (p->scale_dev) u.flags |= fdk::kPostScale; break;
       default: return false;
     }
+  }
+  if (fused) {
+    u.flags |= fdk::kFuseLambda;
+    u.f1 = p->f_fwd[dir];
+    u.f2 = p->f_bwd[dir];
+    u.pf1 = p->p_fwd[dir];
+    u.pf2 = p->p_bwd[dir];
+  } else {
+    u.f1 = fwd ? p->f_fwd[dir] : p->f_bwd[dir];
+    u.pf1 = fwd ? p->p_fwd[dir] : p->p_bwd[dir];
   }
   u.MT = p->MT[dir];
   u.KS = p->KS[dir];
@@ -101,9 +113,12 @@ bool unit_pass(const fd_plan_s* p, const fd_work& wk, int stage, fdk::PassDesc& 
     u.d[i] = p->d_dev[i];
     u.w[i] = p->lam_w[i];
   }
-  const int64_t NQ = int64_t(u.A) * u.B;
-  u.tiles_per_rhs = int32_t((NQ + fdk::kTileP - 1) / fdk::kTileP);
   return true;
+}
+
+int stage_mode(const fdk::PassDesc& u) {
+  if (u.flags & fdk::kFuseLambda) return 2;
+  return u.A == 1 ? 0 : 1;
 }
 
 fd_status validate_work(const fd_work& wk) {
@@ -122,6 +137,11 @@ fd_status validate_work(const fd_work& wk) {
 }
 
 fd_status run_work(int count, const fd_work* work, hipStream_t stream) {
+  // FD_KERNEL=v1 / v2 caps the kernel family (diagnostics and tests of the
+  // fallbacks); the default picks the most capable family a unit fits.
+  const char* kenv = std::getenv("FD_KERNEL");
+  const int kernel_family = (kenv && std::strcmp(kenv, "v1") == 0) ? 1
+                          : (kenv && std::strcmp(kenv, "v2") == 0) ? 2 : 3;
   for (int i = 0; i < count; ++i) {
     fd_status s = validate_work(work[i]);
     if (s != FD_OK) return s;
@@ -146,37 +166,86 @@ fd_status run_work(int count, const fd_work* work, hipStream_t stream) {
       }
     }
     for (int prec = 0; prec <= 5; ++prec) {
-      fdk::PassArgs args;
-      args.count = 0;
-      args.total_tiles = 0;
-      int max_mt = 1;
-      auto flush = [&]() -> fd_status {
-        if (args.count == 0) return FD_OK;
-        hipError_t e = fdk::launch_pass(args, prec, max_mt, stream);
-        args.count = 0;
-        args.total_tiles = 0;
-        max_mt = 1;
-        if (e != hipSuccess) return hip_fail(e, "kernel launch");
-        return FD_OK;
-      };
+      // units of this stage and precision class
+      std::vector<fdk::PassDesc> units;
+      int mode = -1;
       for (int i = 0; i < count; ++i) {
         const fd_work& wk = work[i];
         if (wk.nrhs == 0 || wk.plan->prec != prec) continue;
         fdk::PassDesc u;
         if (!unit_pass(wk.plan, wk, stage, u)) continue;
-        const int64_t tiles = int64_t(u.tiles_per_rhs) * wk.nrhs;
-        if (args.count == fdk::kMaxDesc || int64_t(args.total_tiles) + tiles > 0x7fffffffLL) {
-          fd_status s = flush();
-          if (s != FD_OK) return s;
-        }
-        if (tiles > 0x7fffffffLL) return fail(FD_E_ARG, "fd_apply: too many tiles in one call");
-        u.tile_begin = args.total_tiles;
-        args.u[args.count++] = u;
-        args.total_tiles += int32_t(tiles);
-        max_mt = std::max(max_mt, u.MT);
+        units.push_back(u);
+        mode = stage_mode(u);
       }
-      fd_status s = flush();
-      if (s != FD_OK) return s;
+      if (units.empty()) continue;
+      // Kernel families: 3 = pipelined LDS GEMM (FP64/FP32), 2 = factor resident
+      // in LDS, 1 = factor fragments from global memory. 3 and 2 are
+      // specialised on the row-tile count: one launch per (family, count).
+      std::vector<int> group(units.size(), -1);  // family * 100 + row tiles
+      for (size_t k = 0; k < units.size(); ++k) {
+        int b = 0, c = 0;
+        size_t sm = 0;
+        const bool pre = (units[k].flags & fdk::kPreScale) != 0;
+        // the pipelined family covers the pencil-fast and fused passes; the
+        // contracted-index-fastest passes run faster on family 2 today
+        if (kernel_family >= 3 && mode != 0 && !pre && fdk::v3_plan(prec, mode, units[k].n, units[k].MT, &c, &sm))
+          group[k] = 300 + units[k].MT;
+        else if (kernel_family >= 2 && fdk::v2_plan(prec, mode, units[k].n, units[k].MT, &b, &c, &sm))
+          group[k] = 200 + b;
+        else
+          group[k] = 100;
+      }
+      std::vector<int> keys(group.begin(), group.end());
+      std::sort(keys.begin(), keys.end());
+      keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+      for (int key : keys) {
+        const int fam = key / 100;
+        int max_n = 0, max_mt = 1;
+        for (size_t k = 0; k < units.size(); ++k)
+          if (group[k] == key) {
+            max_n = std::max(max_n, units[k].n);
+            max_mt = std::max(max_mt, units[k].MT);
+          }
+        int bucket = 0, chunk = fdk::kTileP;
+        size_t smem = 0;
+        bool ok = true;
+        if (fam == 3) ok = fdk::v3_plan(prec, mode, max_n, key % 100, &chunk, &smem);
+        if (fam == 2) ok = fdk::v2_plan(prec, mode, max_n, max_mt, &bucket, &chunk, &smem);
+        if (!ok) return fail(FD_E_HIP, "internal: kernel plan changed");
+        fdk::PassArgs args;
+        args.count = 0;
+        args.total_tiles = 0;
+        int launch_mt = 1;
+        auto flush = [&]() -> fd_status {
+          if (args.count == 0) return FD_OK;
+          hipError_t e = fam == 3 ? fdk::launch_pass3(args, prec, mode, key % 100, smem, stream)
+                       : fam == 2 ? fdk::launch_pass2(args, prec, mode, bucket, smem, stream)
+                                  : fdk::launch_pass(args, prec, launch_mt, stream);
+          args.count = 0;
+          args.total_tiles = 0;
+          launch_mt = 1;
+          if (e != hipSuccess) return hip_fail(e, "kernel launch");
+          return FD_OK;
+        };
+        for (size_t k = 0; k < units.size(); ++k) {
+          if (group[k] != key) continue;
+          fdk::PassDesc u = units[k];
+          const int64_t NQ = int64_t(u.A) * u.B;
+          u.tiles_per_rhs = int32_t((NQ + chunk - 1) / chunk);
+          const int64_t tiles = int64_t(u.tiles_per_rhs) * u.nrhs;
+          if (tiles > 0x7fffffffLL) return fail(FD_E_ARG, "fd_apply: too many tiles in one call");
+          if (args.count == fdk::kMaxDesc || int64_t(args.total_tiles) + tiles > 0x7fffffffLL) {
+            fd_status s = flush();
+            if (s != FD_OK) return s;
+          }
+          u.tile_begin = args.total_tiles;
+          args.u[args.count++] = u;
+          args.total_tiles += int32_t(tiles);
+          launch_mt = std::max(launch_mt, u.MT);
+        }
+        fd_status s = flush();
+        if (s != FD_OK) return s;
+      }
     }
     if (rec.start) {
       hipError_t e = hipEventRecord(rec.end, stream);
@@ -274,6 +343,12 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
       return fail(FD_E_ARG, "fd_setup: weights must be > 0");
     }
   }
+  // Buffer offsets inside one vector are 32-bit byte offsets with an
+  // always-out-of-range value at 2^31: N * 8 bytes must stay below it.
+  if (p->N >= (int64_t(1) << 28)) {
+    delete p;
+    return fail(FD_E_ARG, "fd_setup: prod(n) must be below 2^28");
+  }
   // Step 1 of Algorithm 1 in FP64 on the host.
   for (int i = 0; i < ndim; ++i) {
     p->U[i].resize(size_t(n[i]) * n[i]);
@@ -336,7 +411,7 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
   }
   // Pack U_i^T (forward) and U_i (backward) in fragment order.
   const int ks = fdk::mfma_kstep(p->prec);
-  size_t off[3][2], offd[3], offs = 0, total = 0;
+  size_t off[3][2], offp[3][2], offd[3], offs = 0, total = 0;
   auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
   for (int i = 0; i < ndim; ++i) {
     p->MT[i] = (n[i] + 15) / 16;
@@ -344,6 +419,9 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
     const size_t pb = fdk::packed_bytes(n[i], p->prec);
     off[i][0] = total; total = align(total + pb);
     off[i][1] = total; total = align(total + pb);
+    const size_t qb = fdk::plain_bytes(n[i], p->prec);
+    offp[i][0] = total; total = align(total + qb);
+    offp[i][1] = total; total = align(total + qb);
     offd[i] = total; total = align(total + sizeof(double) * n[i]);
   }
   const size_t eb = io_is_f64(p->prec) ? 8 : 4;
@@ -357,6 +435,8 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
       for (int c = 0; c < m; ++c) Ft[r + size_t(m) * c] = p->U[i][c + size_t(m) * r];
     fdk::pack_factor(m, Ft.data(), p->prec, host.data() + off[i][0]);
     fdk::pack_factor(m, p->U[i].data(), p->prec, host.data() + off[i][1]);
+    fdk::plain_factor(m, Ft.data(), p->prec, host.data() + offp[i][0]);
+    fdk::plain_factor(m, p->U[i].data(), p->prec, host.data() + offp[i][1]);
     std::memcpy(host.data() + offd[i], dl[i].data(), sizeof(double) * m);
   }
   if (diag_target) {
@@ -382,6 +462,8 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
   for (int i = 0; i < ndim; ++i) {
     p->f_fwd[i] = base + off[i][0];
     p->f_bwd[i] = base + off[i][1];
+    p->p_fwd[i] = base + offp[i][0];
+    p->p_bwd[i] = base + offp[i][1];
     p->d_dev[i] = reinterpret_cast<const double*>(base + offd[i]);
   }
   if (diag_target) p->scale_dev = base + offs;

@@ -31,6 +31,8 @@ struct PassDesc {
   void* out;
   const void* f1;       // packed factor fragments of the (first) mode product
   const void* f2;       // packed factor fragments of the second product (fused pass)
+  const void* pf1;      // plain row-major factor (LDS-resident kernels), hi then lo plane
+  const void* pf2;      // plain row-major factor of the second product
   const void* scale;    // pre/post scale vector (N entries, I/O type)
   const double* d[3];   // eigenvalues per direction (fused pass)
   double w[3];          // direction weights (fused pass)
@@ -54,6 +56,21 @@ struct PassArgs {
 // Storage/compute class of a plan: 0 = FP64 MFMA, 1 = FP32 MFMA,
 // 2 = BF16 MFMA, 3 = FP16 MFMA, 4 = BF16 split, 5 = FP16 split.
 hipError_t launch_pass(const PassArgs& args, int prec, int max_mt, hipStream_t stream);
+
+// LDS-resident-factor kernels. mode: 0 contracted index fastest, 1 pencil
+// index fastest, 2 fused last mode. v2_plan() picks the row-tile bucket and
+// reports the pencils per workgroup and LDS bytes, or returns false when the
+// factor does not fit in LDS.
+bool v2_plan(int prec, int mode, int max_n, int max_mt, int* bucket, int* chunk, size_t* smem);
+hipError_t launch_pass2(const PassArgs& args, int prec, int mode, int bucket, size_t smem,
+                        hipStream_t stream);
+// Pipelined kernels (FP64/FP32, factor and pencil blocks streamed into LDS
+// stages by direct global->LDS loads). mt is the exact row-tile count.
+bool v3_plan(int prec, int mode, int max_n, int mt, int* chunk, size_t* smem);
+hipError_t launch_pass3(const PassArgs& args, int prec, int mode, int mt, size_t smem, hipStream_t stream);
+// Bytes of one plain factor (n x n in the storage type, hi and lo planes for split).
+size_t plain_bytes(int n, int prec);
+void plain_factor(int n, const double* F, int prec, void* dst);
 
 // Bytes of one packed factor (fragment order) for order n and precision.
 size_t packed_bytes(int n, int prec);

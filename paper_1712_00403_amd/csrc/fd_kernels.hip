@@ -4,6 +4,7 @@
 #include <cstring>
 
 #include "fd_internal.h"
+#include "fd_pass3.inc"
 
 namespace fdk {
 
@@ -14,6 +15,113 @@ extern template hipError_t launch_p<2>(const PassArgs&, int, hipStream_t);
 extern template hipError_t launch_p<3>(const PassArgs&, int, hipStream_t);
 extern template hipError_t launch_p<4>(const PassArgs&, int, hipStream_t);
 extern template hipError_t launch_p<5>(const PassArgs&, int, hipStream_t);
+
+static size_t elem_bytes(int prec);
+static uint16_t to_bf16(float x);
+static float from_bf16(uint16_t h);
+
+template <int P>
+hipError_t launch2_p(const PassArgs& args, int mode, int mt_bucket, size_t smem, hipStream_t stream);
+extern template hipError_t launch2_p<0>(const PassArgs&, int, int, size_t, hipStream_t);
+extern template hipError_t launch2_p<1>(const PassArgs&, int, int, size_t, hipStream_t);
+extern template hipError_t launch2_p<2>(const PassArgs&, int, int, size_t, hipStream_t);
+extern template hipError_t launch2_p<3>(const PassArgs&, int, int, size_t, hipStream_t);
+extern template hipError_t launch2_p<4>(const PassArgs&, int, int, size_t, hipStream_t);
+extern template hipError_t launch2_p<5>(const PassArgs&, int, int, size_t, hipStream_t);
+
+template <int P>
+static bool v2_plan_p(int mode, int max_n, int max_mt, int* bucket, int* chunk, size_t* smem) {
+  const int b = v2_mt<P>(max_mt);
+  if (b > v2_max_mt<P>()) return false;
+  const size_t bytes = v2_lds_bytes<P>(max_n, mode == 2);
+  if (bytes > 160 * 1024) return false;
+  *bucket = b;
+  *chunk = kV2Waves * 16 * v2_pt<P>(b, mode);
+  *smem = bytes;
+  return true;
+}
+
+template <int P>
+hipError_t launch3_p(const PassArgs& args, int mode, int mt, size_t smem, hipStream_t stream);
+extern template hipError_t launch3_p<0>(const PassArgs&, int, int, size_t, hipStream_t);
+extern template hipError_t launch3_p<1>(const PassArgs&, int, int, size_t, hipStream_t);
+
+template <int P>
+static bool v3_plan_p(int mode, int max_n, int mt, int* chunk, size_t* smem) {
+  if (mt < 1 || mt > v2_max_mt<P>()) return false;
+  (void)max_n;
+  const size_t bytes = v3_lds_bytes<P>(mt, mode);
+  if (bytes > 160 * 1024) return false;
+  *chunk = v3_np<P>(mt, mode);
+  *smem = bytes;
+  return true;
+}
+
+bool v3_plan(int prec, int mode, int max_n, int mt, int* chunk, size_t* smem) {
+  if (prec == 0) return v3_plan_p<0>(mode, max_n, mt, chunk, smem);
+  if (prec == 1) return v3_plan_p<1>(mode, max_n, mt, chunk, smem);
+  return false;
+}
+
+hipError_t launch_pass3(const PassArgs& args, int prec, int mode, int mt, size_t smem, hipStream_t stream) {
+  if (args.total_tiles <= 0) return hipSuccess;
+  if (prec == 0) return launch3_p<0>(args, mode, mt, smem, stream);
+  if (prec == 1) return launch3_p<1>(args, mode, mt, smem, stream);
+  return hipErrorInvalidValue;
+}
+
+bool v2_plan(int prec, int mode, int max_n, int max_mt, int* bucket, int* chunk, size_t* smem) {
+  switch (prec) {
+    case 0: return v2_plan_p<0>(mode, max_n, max_mt, bucket, chunk, smem);
+    case 1: return v2_plan_p<1>(mode, max_n, max_mt, bucket, chunk, smem);
+    case 2: return v2_plan_p<2>(mode, max_n, max_mt, bucket, chunk, smem);
+    case 3: return v2_plan_p<3>(mode, max_n, max_mt, bucket, chunk, smem);
+    case 4: return v2_plan_p<4>(mode, max_n, max_mt, bucket, chunk, smem);
+    case 5: return v2_plan_p<5>(mode, max_n, max_mt, bucket, chunk, smem);
+    default: return false;
+  }
+}
+
+hipError_t launch_pass2(const PassArgs& args, int prec, int mode, int bucket, size_t smem,
+                        hipStream_t stream) {
+  if (args.total_tiles <= 0) return hipSuccess;
+  switch (prec) {
+    case 0: return launch2_p<0>(args, mode, bucket, smem, stream);
+    case 1: return launch2_p<1>(args, mode, bucket, smem, stream);
+    case 2: return launch2_p<2>(args, mode, bucket, smem, stream);
+    case 3: return launch2_p<3>(args, mode, bucket, smem, stream);
+    case 4: return launch2_p<4>(args, mode, bucket, smem, stream);
+    case 5: return launch2_p<5>(args, mode, bucket, smem, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+size_t plain_bytes(int n, int prec) {
+  const size_t per = size_t(n) * n * elem_bytes(prec);
+  return (prec == 4 || prec == 5) ? 2 * per : per;
+}
+
+void plain_factor(int n, const double* F, int prec, void* dst) {
+  const size_t nn = size_t(n) * n;
+  for (int r = 0; r < n; ++r)
+    for (int c = 0; c < n; ++c) {
+      const double v = F[r + size_t(n) * c];
+      const size_t idx = size_t(r) * n + c;  // row-major
+      if (prec == 0) {
+        reinterpret_cast<double*>(dst)[idx] = v;
+      } else if (prec == 1) {
+        reinterpret_cast<float*>(dst)[idx] = float(v);
+      } else if (prec == 2 || prec == 4) {
+        const uint16_t h = to_bf16(float(v));
+        reinterpret_cast<uint16_t*>(dst)[idx] = h;
+        if (prec == 4) reinterpret_cast<uint16_t*>(dst)[nn + idx] = to_bf16(float(v - double(from_bf16(h))));
+      } else {
+        const _Float16 h = (_Float16)float(v);
+        reinterpret_cast<_Float16*>(dst)[idx] = h;
+        if (prec == 5) reinterpret_cast<_Float16*>(dst)[nn + idx] = (_Float16)float(v - double((float)h));
+      }
+    }
+}
 
 int mfma_kstep(int prec) { return (prec <= 1) ? 4 : 32; }
 

@@ -199,3 +199,33 @@ def test_full_size_64cube_p3(prec):
         print(f"  block {k}: rel err {err:.3e}")
         assert err < TOL[prec]
     pc.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "bf16_split"])
+def test_global_fragment_kernels(prec, monkeypatch):
+    """The kernels that read packed factor fragments from global memory (FD_KERNEL=v1)."""
+    _case(f"global-fragment kernels, prec={prec}")
+    monkeypatch.setenv("FD_KERNEL", "v1")
+    Ks, Ms = _vel_factors((7, 12, 5), 3)
+    f = FDFactors(Ks, Ms, np.array([1.0, 2.0, 1.0]))
+    plan = _fd().Plan(Ks, Ms, weights=np.array([1.0, 2.0, 1.0]), precision=prec)
+    r = workloads.residuals(16, 2, plan.N)
+    z = _run_plan(plan, r)
+    for j in range(2):
+        assert _rel(z[j], fd_apply(f, r[j])) < TOL[prec]
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "bf16_split"])
+@pytest.mark.parametrize("n_el", [(96, 5, 4), (4, 96, 3), (3, 4, 96)])
+def test_large_factor_96_elements_p4(prec, n_el):
+    """n = 194 in one direction (96 elements, p = 4): factor beyond the FP64 LDS image."""
+    _case(f"n=194 direction, n_el={n_el}, prec={prec}")
+    Ks, Ms = _vel_factors(n_el, 4)
+    f = FDFactors(Ks, Ms, np.array([2.0, 1.0, 1.0]))
+    plan = _fd().Plan(Ks, Ms, weights=np.array([2.0, 1.0, 1.0]), precision=prec)
+    r = workloads.residuals(17, 2, plan.N)
+    z = _run_plan(plan, r)
+    for j in range(2):
+        assert _rel(z[j], fd_apply(f, r[j])) < TOL[prec]
+    plan.close()
