@@ -179,9 +179,10 @@ fd_status run_work(int count, const fd_work* work, hipStream_t stream) {
       }
       if (units.empty()) continue;
       // Kernel families: 3 = pipelined LDS GEMM (FP64/FP32), 2 = factor resident
-      // in LDS, 1 = factor fragments from global memory. 3 and 2 are
-      // specialised on the row-tile count: one launch per (family, count).
-      std::vector<int> group(units.size(), -1);  // family * 100 + row tiles
+      // in LDS, 1 = factor fragments from global memory. Family 3 launches
+      // group units of one factor order n, family 2 units of one row-tile
+      // count; family 1 takes the rest in one launch.
+      std::vector<int> group(units.size(), -1);  // family * 1000 + n or row tiles
       for (size_t k = 0; k < units.size(); ++k) {
         int b = 0, c = 0;
         size_t sm = 0;
@@ -189,17 +190,17 @@ fd_status run_work(int count, const fd_work* work, hipStream_t stream) {
         // the pipelined family covers the pencil-fast and fused passes; the
         // contracted-index-fastest passes run faster on family 2 today
         if (kernel_family >= 3 && mode != 0 && !pre && fdk::v3_plan(prec, mode, units[k].n, units[k].MT, &c, &sm))
-          group[k] = 300 + units[k].MT;
+          group[k] = 3000 + units[k].n;
         else if (kernel_family >= 2 && fdk::v2_plan(prec, mode, units[k].n, units[k].MT, &b, &c, &sm))
-          group[k] = 200 + b;
+          group[k] = 2000 + b;
         else
-          group[k] = 100;
+          group[k] = 1000;
       }
       std::vector<int> keys(group.begin(), group.end());
       std::sort(keys.begin(), keys.end());
       keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
       for (int key : keys) {
-        const int fam = key / 100;
+        const int fam = key / 1000;
         int max_n = 0, max_mt = 1;
         for (size_t k = 0; k < units.size(); ++k)
           if (group[k] == key) {
@@ -209,7 +210,7 @@ fd_status run_work(int count, const fd_work* work, hipStream_t stream) {
         int bucket = 0, chunk = fdk::kTileP;
         size_t smem = 0;
         bool ok = true;
-        if (fam == 3) ok = fdk::v3_plan(prec, mode, max_n, key % 100, &chunk, &smem);
+        if (fam == 3) ok = fdk::v3_plan(prec, mode, max_n, max_mt, &chunk, &smem);
         if (fam == 2) ok = fdk::v2_plan(prec, mode, max_n, max_mt, &bucket, &chunk, &smem);
         if (!ok) return fail(FD_E_HIP, "internal: kernel plan changed");
         fdk::PassArgs args;
@@ -218,7 +219,7 @@ fd_status run_work(int count, const fd_work* work, hipStream_t stream) {
         int launch_mt = 1;
         auto flush = [&]() -> fd_status {
           if (args.count == 0) return FD_OK;
-          hipError_t e = fam == 3 ? fdk::launch_pass3(args, prec, mode, key % 100, smem, stream)
+          hipError_t e = fam == 3 ? fdk::launch_pass3(args, prec, mode, max_mt, smem, stream)
                        : fam == 2 ? fdk::launch_pass2(args, prec, mode, bucket, smem, stream)
                                   : fdk::launch_pass(args, prec, launch_mt, stream);
           args.count = 0;
