@@ -49,3 +49,38 @@ def solve(Ks, Ms, r, weights=None, scale=None):
     if scale is not None:
         z = scale * z
     return z
+
+
+def coefficient_operator(tables, weights, coef, order):
+    """Full Galerkin matrix with pointwise coefficients on a tensor grid (tiny grids only).
+
+    ``tables[t]`` = (B, dB): univariate values and derivatives of direction t
+    at its quadrature points; ``weights[t]`` the quadrature weights. Each
+    multivariate function B_i (i_1 fastest) and its partial derivatives are
+    formed explicitly at every grid point (point index q_1 fastest) as rows
+    of a matrix, and the integral is the weighted sum over points:
+    order 1: sum_{a,b} G_a diag(w c_ab) G_b^T with G_a = [d_a B_i(q)];
+    order 0: G diag(w c) G^T with G = [B_i(q)].
+    ``coef`` is (d, d, P) for order 1, (P,) for order 0.
+    """
+    d = len(tables)
+    W = np.ones(1)
+    for t in range(d):
+        W = np.kron(weights[t], W)
+
+    def rows(a):
+        G = np.ones((1, 1))
+        for t in range(d):
+            B, dB = tables[t]
+            G = np.kron(dB if t == a else B, G)
+        return G
+
+    if order == 0:
+        G = rows(-1)
+        return (G * (W * coef)[None, :]) @ G.T
+    grads = [rows(a) for a in range(d)]
+    A = 0.0
+    for a in range(d):
+        for b in range(d):
+            A = A + (grads[a] * (W * coef[a, b])[None, :]) @ grads[b].T
+    return A

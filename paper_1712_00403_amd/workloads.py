@@ -12,7 +12,7 @@ homogeneous Dirichlet conditions (first and last univariate function
 dropped), the pressure space has degree p and no boundary condition.
 """
 from dataclasses import dataclass, field
-from typing import List, Optional, Tuple
+from typing import Callable, List, Optional, Tuple
 
 import numpy as np
 
@@ -109,3 +109,104 @@ def batch_patches(count=256, seed=3):
 def batch_residuals(rng, sizes):
     """One Gaussian residual per patch, drawn in patch order after the descriptors."""
     return [rng.standard_normal(int(n)) for n in sizes]
+
+
+# ---------------------------------------------------------------------------
+# Geometries and viscosities for the coefficient-aware blocks. A geometry is
+# the parametrisation G of the patch (its map and Jacobian, evaluated at
+# parametric points) and the kinematic viscosity nu at physical points. These
+# are problem data: the preconditioner only sees their values at quadrature
+# points.
+
+@dataclass(frozen=True)
+class Geometry:
+    """Parametrisation G of the unit square/cube and a viscosity nu(x).
+
+    ``map(eta)`` and ``jacobian(eta)`` take parametric points of shape (P, d);
+    ``jacobian`` returns J[p, a, b] = dG_a/deta_b. ``nu(x)`` takes physical
+    points (P, d) and returns (P,).
+    """
+    name: str
+    ndim: int
+    map: Callable
+    jacobian: Callable
+    nu: Callable
+
+
+def _const_nu(c):
+    return lambda x: np.full(x.shape[0], float(c))
+
+
+def identity_geometry(ndim, nu=None):
+    """G = id with nu = 1 unless given."""
+    return Geometry("identity", ndim, lambda e: np.array(e, dtype=np.float64),
+                    lambda e: np.broadcast_to(np.eye(ndim), (e.shape[0], ndim, ndim)).copy(),
+                    nu or _const_nu(1.0))
+
+
+def affine_geometry(A, nu=None):
+    """G(eta) = A eta (constant Jacobian A)."""
+    A = np.array(A, dtype=np.float64)
+    d = A.shape[0]
+    return Geometry("affine", d, lambda e: e @ A.T,
+                    lambda e: np.broadcast_to(A, (e.shape[0], d, d)).copy(), nu or _const_nu(1.0))
+
+
+def sine_geometry(ndim, amp=0.1, nu=None):
+    """Axis-separable map G(eta)_j = eta_j + amp sin(pi eta_j).
+
+    The Jacobian is diagonal with entries 1 + amp pi cos(pi eta_j) (positive
+    for amp < 1/pi). Default viscosity: nu(x) = 1 + 0.5 sin(2 pi x_1) cos(2 pi x_2).
+    """
+    def jac(e):
+        J = np.zeros((e.shape[0], ndim, ndim))
+        for j in range(ndim):
+            J[:, j, j] = 1.0 + amp * np.pi * np.cos(np.pi * e[:, j])
+        return J
+    return Geometry("sine", ndim, lambda e: e + amp * np.sin(np.pi * e), jac, nu or wavy_viscosity)
+
+
+def wavy_viscosity(x):
+    """nu(x) = 1 + 0.5 sin(2 pi x_1) cos(2 pi x_2): positive, not separable."""
+    return 1.0 + 0.5 * np.sin(2.0 * np.pi * x[:, 0]) * np.cos(2.0 * np.pi * x[:, 1])
+
+
+def separable_viscosity(x):
+    """nu(x) = (1 + x_1^2) exp(x_2) (2 + x_3): a product of one-variable factors."""
+    v = (1.0 + x[:, 0] ** 2) * np.exp(x[:, 1])
+    if x.shape[1] > 2:
+        v = v * (2.0 + x[:, 2])
+    return v
+
+
+def warped_geometry(ndim, nu=None):
+    """A curved map with a full, varying Jacobian (off-diagonal coefficients).
+
+    2D: G = (eta_1 + 0.1 eta_2^2, eta_2 + 0.05 sin(pi eta_1));
+    3D adds G_3 = eta_3 (1 + 0.1 eta_1).
+    """
+    def gmap(e):
+        x = np.array(e, dtype=np.float64)
+        x[:, 0] = e[:, 0] + 0.1 * e[:, 1] ** 2
+        x[:, 1] = e[:, 1] + 0.05 * np.sin(np.pi * e[:, 0])
+        if ndim == 3:
+            x[:, 2] = e[:, 2] * (1.0 + 0.1 * e[:, 0])
+        return x
+
+    def jac(e):
+        J = np.zeros((e.shape[0], ndim, ndim))
+        J[:, 0, 0] = 1.0
+        J[:, 0, 1] = 0.2 * e[:, 1]
+        J[:, 1, 0] = 0.05 * np.pi * np.cos(np.pi * e[:, 0])
+        J[:, 1, 1] = 1.0
+        if ndim == 3:
+            J[:, 2, 0] = 0.1 * e[:, 2]
+            J[:, 2, 2] = 1.0 + 0.1 * e[:, 0]
+        return J
+    return Geometry("warped", ndim, gmap, jac, nu or _const_nu(1.0))
+
+
+def tensor_points(axes):
+    """All points of the tensor grid of 1D point arrays ``axes``, axis 1 fastest: (P, d)."""
+    grids = np.meshgrid(*axes, indexing="ij")
+    return np.stack([g.reshape(-1, order="F") for g in grids], axis=1)
