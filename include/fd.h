@@ -113,6 +113,55 @@ fd_status fd_quadrature_1d(int32_t n_el, int32_t npts, double* x, double* w);
  * fails). Host computation only; needs no GPU. */
 fd_status fd_factor_1d(int32_t n, const double* K, const double* M, double* U, double* d);
 
+/* ------------------------------------------- coefficient-aware blocks */
+
+/* Coefficient matrices of the TH velocity blocks (Sec. 3, eq. Q_TH):
+ * C_k = nu (J^{-1} J^{-T} + D_k D_k^T) |det J|, D_k = J^{-1} e_k, and the
+ * TH pressure-mass weight nu^{-1} |det J| (eq. weighted-pressure-mass), at
+ * npts points.
+ *  jac : host, npts * ndim * ndim, point-major, row-major per point:
+ *        jac[(p*ndim + a)*ndim + b] = dG_a / deta_b.
+ *  nu  : host, npts viscosity values at the physical points G(eta_p).
+ *  C   : host output or NULL, ndim^3 * npts, field-major:
+ *        C[((k*ndim + a)*ndim + b)*npts + p] = (C_k)_{ab} at point p.
+ *  q_weight: host output or NULL, npts.
+ * Errors: FD_E_ARG (ndim not 2 or 3, npts < 1, NULL inputs, a singular
+ * Jacobian or nu <= 0 at some point). Host computation only. */
+fd_status fd_geometry_coefficients(int32_t ndim, int64_t npts, const double* jac, const double* nu,
+                                   double* C, double* q_weight);
+
+/* Separable approximation of the diagonal of one C_k (Appendix):
+ * c_jj(eta) ~ tau_j(eta_j) prod_{i != j} mu_i(eta_i) on a tensor grid of
+ * nq[0] x .. x nq[ndim-1] quadrature points (direction 1 fastest).
+ *  c     : host, entry j's field starts at c + j*stride (stride >= prod nq);
+ *          for C_k as laid out by fd_geometry_coefficients, c = C +
+ *          k*ndim*ndim*npts and stride = (ndim + 1)*npts. Entries must be > 0.
+ *  sweeps, tol: at most `sweeps` sweeps of the alternating midrange
+ *          (Diliberto-Straus) fit of log c_jj, stopping early once no
+ *          factor value moves by more than tol (in log scale).
+ *  tau, mu: host outputs, sum(nq) values, direction 1's points first.
+ * The non-tau factors of each fit are normalised to geometric mean 1 (the
+ * constant goes into tau_j) and mu_i is the geometric mean of the estimates
+ * from the entries j != i. Errors: FD_E_ARG. Host computation only. */
+fd_status fd_separable_factors(int32_t ndim, const int32_t* nq, const double* c, int64_t stride,
+                               int32_t sweeps, double tol, double* tau, double* mu);
+
+/* Diagonal of a Galerkin operator with pointwise coefficients on the
+ * tensor-product spline space of fd_assemble_1d's (n_el[i], degree,
+ * regularity, dirichlet) in every direction, with the quadrature grid of
+ * npts Gauss points per element (npts <= 0: degree + 1):
+ *  order 1: [A]_ii = int sum_{a,b} c_ab d_a B_i d_b B_i, coef holds ndim^2
+ *           fields, field (a, b) at coef + (a*ndim + b)*P (the layout of one
+ *           C_k from fd_geometry_coefficients), P = prod(n_el[i]*npts);
+ *  order 0: [Q]_ii = int c B_i^2, coef holds one field of P values.
+ * Fields are on the grid with direction 1 fastest, element-major points per
+ * direction. diag: host output, prod(n_i) values, i_1 fastest. This is
+ * diag(A_kk) for D_V and diag(Q) for D_Q (Sec. 6): pass it to fd_setup as
+ * diag_target. Errors: FD_E_ARG. Host computation only. */
+fd_status fd_operator_diagonal(int32_t ndim, const int32_t* n_el, int32_t degree, int32_t regularity,
+                               int32_t dirichlet, int32_t npts, int32_t order, const double* coef,
+                               double* diag);
+
 /* ---------------------------------------------------------------- plans */
 
 /* Build a plan for one block (1) with ndim in {2, 3} directions.

@@ -14,7 +14,7 @@ BUILD = os.path.join(HERE, "_build")
 OUT = os.path.join(HERE, "libfd.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["fd_api.hip", "fd_kernels.hip", "fd_host.cpp", "fd_pass_f64.hip", "fd_pass_f32.hip",
+SOURCES = ["fd_api.hip", "fd_kernels.hip", "fd_host.cpp", "fd_geometry.cpp", "fd_pass_f64.hip", "fd_pass_f32.hip",
            "fd_pass_bf16.hip", "fd_pass_f16.hip", "fd_pass_bf16s.hip", "fd_pass_f16s.hip"]
 
 COMMON = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

@@ -306,6 +306,30 @@ fd_status fd_quadrature_1d(int32_t n_el, int32_t npts, double* x, double* w) {
   return FD_OK;
 }
 
+fd_status fd_geometry_coefficients(int32_t ndim, int64_t npts, const double* jac, const double* nu,
+                                   double* C, double* q_weight) {
+  const int rc = fdh::geometry_coefficients(ndim, npts, jac, nu, C, q_weight);
+  if (rc == 1) return fail(FD_E_ARG, "fd_geometry_coefficients: bad arguments");
+  if (rc == 2) return fail(FD_E_ARG, "fd_geometry_coefficients: singular Jacobian or nu <= 0");
+  return FD_OK;
+}
+
+fd_status fd_separable_factors(int32_t ndim, const int32_t* nq, const double* c, int64_t stride,
+                               int32_t sweeps, double tol, double* tau, double* mu) {
+  const int rc = fdh::separable_factors(ndim, nq, c, stride, sweeps, tol, tau, mu);
+  if (rc == 1) return fail(FD_E_ARG, "fd_separable_factors: bad arguments");
+  if (rc == 2) return fail(FD_E_ARG, "fd_separable_factors: coefficient entry <= 0");
+  return FD_OK;
+}
+
+fd_status fd_operator_diagonal(int32_t ndim, const int32_t* n_el, int32_t degree, int32_t regularity,
+                               int32_t dirichlet, int32_t npts, int32_t order, const double* coef,
+                               double* diag) {
+  if (fdh::operator_diagonal(ndim, n_el, degree, regularity, dirichlet, npts, order, coef, diag))
+    return fail(FD_E_ARG, "fd_operator_diagonal: bad arguments");
+  return FD_OK;
+}
+
 fd_status fd_factor_1d(int32_t n, const double* K, const double* M, double* U, double* d) {
   const char* why = "";
   const int rc = fdh::factor_1d(n, K, M, U, d, &why);

@@ -96,6 +96,66 @@ static void nonzero_basis(const std::vector<double>& t, int span, int degree, do
   }
 }
 
+// Values N and first derivatives dN of the degree+1 functions that do not
+// vanish on knot span `span`; derivative by differentiating the recursion:
+// b'_{k,p} = p/(t_{k+p}-t_k) b_{k,p-1} - p/(t_{k+p+1}-t_{k+1}) b_{k+1,p-1}.
+static void nonzero_basis_ders(const std::vector<double>& t, int span, int degree, double x, double* N,
+                               double* dN) {
+  double Nl[32];
+  nonzero_basis(t, span, degree, x, N);
+  nonzero_basis(t, span, degree - 1, x, Nl);  // functions span-degree+1 .. span
+  for (int j = 0; j <= degree; ++j) {
+    const int k = span - degree + j;
+    const double lo = (j >= 1) ? Nl[j - 1] : 0.0;        // b_{k,p-1}
+    const double hi = (j <= degree - 1) ? Nl[j] : 0.0;   // b_{k+1,p-1}
+    const double d1 = t[k + degree] - t[k];
+    const double d2 = t[k + degree + 1] - t[k + 1];
+    dN[j] = (d1 != 0.0 ? degree / d1 * lo : 0.0) - (d2 != 0.0 ? degree / d2 * hi : 0.0);
+  }
+}
+
+int basis_tables(int n_el, int degree, int regularity, int dirichlet, int npts, int* m_out,
+                 std::vector<double>& B, std::vector<double>& dB, std::vector<int>& qlo,
+                 std::vector<int>& qhi) {
+  if (n_el < 1 || degree < 1 || degree > 12 || regularity < -1 || regularity >= degree) return 1;
+  if (npts <= 0 || npts > 16) return 1;
+  const std::vector<double> t = knots_open_uniform(n_el, degree, regularity);
+  const int m_full = int(t.size()) - degree - 1;
+  const int off = dirichlet ? 1 : 0;
+  const int m = m_full - 2 * off;
+  if (m < 1) return 1;
+  *m_out = m;
+  const int nq = n_el * npts;
+  B.assign(size_t(m) * nq, 0.0);
+  dB.assign(size_t(m) * nq, 0.0);
+  qlo.assign(m, nq);
+  qhi.assign(m, 0);
+  std::vector<double> xq(nq), wq(nq);
+  element_quadrature(n_el, npts, xq.data(), wq.data());
+  const int mult = degree - regularity;
+  double N[32], dN[32];
+  for (int e = 0; e < n_el; ++e) {
+    const int span = degree + mult * e;
+    for (int q = 0; q < npts; ++q) {
+      const int iq = e * npts + q;
+      nonzero_basis_ders(t, span, degree, xq[iq], N, dN);
+      for (int j = 0; j <= degree; ++j) {
+        const int r = span - degree + j - off;
+        if (r < 0 || r >= m) continue;
+        B[size_t(r) * nq + iq] = N[j];
+        dB[size_t(r) * nq + iq] = dN[j];
+      }
+    }
+    for (int j = 0; j <= degree; ++j) {
+      const int r = span - degree + j - off;
+      if (r < 0 || r >= m) continue;
+      qlo[r] = std::min(qlo[r], e * npts);
+      qhi[r] = std::max(qhi[r], (e + 1) * npts);
+    }
+  }
+  return 0;
+}
+
 int assemble_1d(int n_el, int degree, int regularity, int dirichlet, int npts, const double* tau_q,
                 const double* mu_q, int* m_out, double* K, double* M) {
   if (n_el < 1 || degree < 1 || degree > 12 || regularity < -1 || regularity >= degree) return 1;
@@ -112,23 +172,13 @@ int assemble_1d(int n_el, int degree, int regularity, int dirichlet, int npts, c
   std::vector<double> xq(size_t(n_el) * npts), wq(size_t(n_el) * npts);
   element_quadrature(n_el, npts, xq.data(), wq.data());
   const int mult = degree - regularity;
-  double N[32], Nl[32], dN[32];
+  double N[32], dN[32];
   for (int e = 0; e < n_el; ++e) {
     const int span = degree + mult * e;  // last knot index equal to e / n_el
     for (int q = 0; q < npts; ++q) {
       const size_t iq = size_t(e) * npts + q;
       const double x = xq[iq];
-      nonzero_basis(t, span, degree, x, N);
-      // derivative: b'_{k,p} = p/(t_{k+p}-t_k) b_{k,p-1} - p/(t_{k+p+1}-t_{k+1}) b_{k+1,p-1}
-      nonzero_basis(t, span, degree - 1, x, Nl);  // functions span-degree+1 .. span
-      for (int j = 0; j <= degree; ++j) {
-        const int k = span - degree + j;
-        const double lo = (j >= 1) ? Nl[j - 1] : 0.0;        // b_{k,p-1}
-        const double hi = (j <= degree - 1) ? Nl[j] : 0.0;   // b_{k+1,p-1}
-        const double d1 = t[k + degree] - t[k];
-        const double d2 = t[k + degree + 1] - t[k + 1];
-        dN[j] = (d1 != 0.0 ? degree / d1 * lo : 0.0) - (d2 != 0.0 ? degree / d2 * hi : 0.0);
-      }
+      nonzero_basis_ders(t, span, degree, x, N, dN);
       const double wk = wq[iq] * (tau_q ? tau_q[iq] : 1.0);
       const double wm = wq[iq] * (mu_q ? mu_q[iq] : 1.0);
       for (int a = 0; a <= degree; ++a)

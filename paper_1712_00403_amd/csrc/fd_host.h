@@ -2,6 +2,7 @@
 #pragma once
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 namespace fdh {
 
@@ -22,5 +23,27 @@ int assemble_1d(int n_el, int degree, int regularity, int dirichlet, int npts, c
 // K may be null (d = 0). Returns 0, 1 (bad argument / asymmetric) or
 // 2 (M not positive definite); *why names the failure.
 int factor_1d(int n, const double* K, const double* M, double* U, double* d, const char** why);
+
+// Dense tables of the kept univariate functions at the quadrature points:
+// B, dB are m x (n_el*npts) row-major (row = function after dropping the end
+// functions when `dirichlet`), [qlo[i], qhi[i]) the quadrature points of the
+// elements in the support of function i. Returns 0, or 1 on bad arguments.
+int basis_tables(int n_el, int degree, int regularity, int dirichlet, int npts, int* m_out,
+                 std::vector<double>& B, std::vector<double>& dB, std::vector<int>& qlo,
+                 std::vector<int>& qhi);
+
+// Coefficient matrices C_k of the velocity blocks and the pressure-mass
+// weight at P points (fd_geometry_coefficients). 0, 1 (arguments) or
+// 2 (singular Jacobian or nu <= 0 at some point).
+int geometry_coefficients(int d, int64_t P, const double* jac, const double* nu, double* C, double* qw);
+
+// Separable factors of the d diagonal entries of one C_k (fd_separable_factors).
+// 0, 1 (arguments) or 2 (an entry <= 0).
+int separable_factors(int d, const int* nq, const double* c, int64_t stride, int sweeps, double tol,
+                      double* tau, double* mu);
+
+// Diagonal of a tensor-product Galerkin operator (fd_operator_diagonal). 0 or 1.
+int operator_diagonal(int d, const int* n_el, int degree, int regularity, int dirichlet, int npts,
+                      int order, const double* coef, double* diag);
 
 }  // namespace fdh

@@ -20,7 +20,8 @@ STATUS_NAMES = {0: "FD_OK", 1: "FD_E_ARG", 2: "FD_E_NOTSPD", 3: "FD_E_NOMEM", 4:
                 5: "FD_E_UNSUPPORTED"}
 
 # every symbol declared in include/fd.h
-EXPORTS = ("fd_assemble_1d", "fd_quadrature_1d", "fd_factor_1d", "fd_setup", "fd_destroy",
+EXPORTS = ("fd_assemble_1d", "fd_quadrature_1d", "fd_factor_1d", "fd_geometry_coefficients",
+           "fd_separable_factors", "fd_operator_diagonal", "fd_setup", "fd_destroy",
            "fd_plan_size", "fd_plan_device_bytes", "fd_plan_factors", "fd_apply",
            "fd_apply_batched", "fd_timing_enable", "fd_timing_read", "fd_last_error")
 
@@ -53,6 +54,11 @@ def lib():
     L.fd_assemble_1d.argtypes = [ctypes.c_int32] * 5 + [c_dp, c_dp, ctypes.POINTER(ctypes.c_int32), c_dp, c_dp]
     L.fd_quadrature_1d.argtypes = [ctypes.c_int32, ctypes.c_int32, c_dp, c_dp]
     L.fd_factor_1d.argtypes = [ctypes.c_int32, c_dp, c_dp, c_dp, c_dp]
+    L.fd_geometry_coefficients.argtypes = [ctypes.c_int32, ctypes.c_int64, c_dp, c_dp, c_dp, c_dp]
+    L.fd_separable_factors.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), c_dp, ctypes.c_int64,
+                                       ctypes.c_int32, ctypes.c_double, c_dp, c_dp]
+    L.fd_operator_diagonal.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)] + [ctypes.c_int32] * 5 + \
+        [c_dp, c_dp]
     L.fd_setup.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(c_dp),
                            ctypes.POINTER(c_dp), c_dp, c_dp, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]
     L.fd_destroy.argtypes = [ctypes.c_void_p]
@@ -66,7 +72,8 @@ def lib():
     L.fd_apply_batched.argtypes = [ctypes.c_int32, ctypes.POINTER(FDWork), ctypes.c_void_p]
     L.fd_timing_enable.argtypes = [ctypes.c_int32]
     L.fd_timing_read.argtypes = [c_dp, ctypes.POINTER(ctypes.c_int32)]
-    for name in ("fd_timing_enable", "fd_timing_read", "fd_assemble_1d", "fd_quadrature_1d", "fd_factor_1d", "fd_setup", "fd_destroy",
+    for name in ("fd_timing_enable", "fd_timing_read", "fd_assemble_1d", "fd_quadrature_1d", "fd_factor_1d",
+                 "fd_geometry_coefficients", "fd_separable_factors", "fd_operator_diagonal", "fd_setup", "fd_destroy",
                  "fd_plan_factors", "fd_apply", "fd_apply_batched"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -123,6 +130,54 @@ def factor_1d(K, M):
                               Mc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                               U.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _dp(d)))
     return np.ascontiguousarray(U), d
+
+
+def geometry_coefficients(jac, nu, matrices=True):
+    """C (d, d, d, P) with C[k, a, b] = (C_k)_ab at each point, and the pressure weight (P,).
+
+    jac: (P, d, d) Jacobians dG_a/deta_b; nu: (P,) viscosity at the mapped points
+    (see fd_geometry_coefficients). ``matrices=False`` returns (None, weight).
+    """
+    jac = _f64c(jac)
+    P, d, _ = jac.shape
+    nu = _f64c(nu).ravel()
+    C = np.zeros((d, d, d, P)) if matrices else None
+    qw = np.zeros(P)
+    _check(lib().fd_geometry_coefficients(d, P, _dp(jac), _dp(nu), _dp(C), _dp(qw)))
+    return C, qw
+
+
+def separable_factors(Ck, nq, sweeps=20, tol=1e-12):
+    """(tau, mu) of one C_k given as (d, d, P) fields on the nq grid (see fd_separable_factors)."""
+    Ck = _f64c(Ck)
+    d = Ck.shape[0]
+    P = Ck.shape[-1]
+    tau = np.zeros(int(sum(nq)))
+    mu = np.zeros(int(sum(nq)))
+    nqa = (ctypes.c_int32 * d)(*[int(x) for x in nq])
+    _check(lib().fd_separable_factors(d, nqa, _dp(Ck), (d + 1) * P, int(sweeps), float(tol), _dp(tau), _dp(mu)))
+    cuts = np.cumsum([0] + [int(x) for x in nq])
+    return ([tau[cuts[i]:cuts[i + 1]] for i in range(d)], [mu[cuts[i]:cuts[i + 1]] for i in range(d)])
+
+
+def operator_diagonal(n_el, degree, regularity, dirichlet, npts, coef, order):
+    """Diagonal of the Galerkin operator with pointwise coefficients (see fd_operator_diagonal).
+
+    order 1: coef (d, d, P); order 0: coef (P,). Returns the diagonal, i_1 fastest.
+    """
+    d = len(n_el)
+    coef = _f64c(coef)
+    m = ctypes.c_int32(0)
+    N = 1
+    for ne in n_el:
+        _check(lib().fd_assemble_1d(int(ne), degree, regularity, int(bool(dirichlet)), npts, None, None,
+                                    ctypes.byref(m), None, None))
+        N *= m.value
+    diag = np.zeros(N)
+    nea = (ctypes.c_int32 * d)(*[int(x) for x in n_el])
+    _check(lib().fd_operator_diagonal(d, nea, degree, regularity, int(bool(dirichlet)), npts, int(order),
+                                      _dp(coef), _dp(diag)))
+    return diag
 
 
 # ---------------------------------------------------------------- plans

@@ -25,9 +25,14 @@ def block_factors(spec):
 
 
 class BlockPreconditioner:
-    """Plans for every block of a workloads.Problem, sharing 1D factors per block."""
+    """Plans for every block of a workloads.Problem.
 
-    def __init__(self, problem, precision="f64", diag_targets=None, factors=None):
+    ``factors`` / ``weights`` / ``diag_targets`` (one entry per block) replace
+    the simple blocks' factors, direction weights and (absent) diagonal
+    scalings, e.g. with those of the coefficient-aware blocks (``geometry``).
+    """
+
+    def __init__(self, problem, precision="f64", diag_targets=None, factors=None, weights=None):
         self.problem = problem
         self.precision = precision
         self.plans = []
@@ -35,7 +40,8 @@ class BlockPreconditioner:
         for bi, spec in enumerate(problem.blocks):
             Ks, Ms = factors[bi] if factors is not None else block_factors(spec)
             dt = None if diag_targets is None else diag_targets[bi]
-            plan = fd.Plan(Ks, Ms, weights=np.asarray(spec.weights), diag_target=dt, precision=precision)
+            w = np.asarray(spec.weights if weights is None else weights[bi], dtype=np.float64)
+            plan = fd.Plan(Ks, Ms, weights=w, diag_target=dt, precision=precision)
             self.plans.append(plan)
             self.sizes.append(plan.N)
         self.offsets = np.concatenate([[0], np.cumsum(self.sizes)]).astype(np.int64)

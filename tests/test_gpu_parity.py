@@ -229,3 +229,30 @@ def test_large_factor_96_elements_p4(prec, n_el):
     for j in range(2):
         assert _rel(z[j], fd_apply(f, r[j])) < TOL[prec]
     plan.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("ndim,n_el,p,geo", [(3, (6, 9, 5), 2, "sine"), (3, (5, 4, 7), 3, "warped"),
+                                              (2, (12, 9), 2, "warped")])
+def test_geometry_variant_block_apply(prec, ndim, n_el, p, geo):
+    """Coefficient-aware P_D: per-component factors, D_V / D_Q scalings (Sec. 6, Appendix)."""
+    _case(f"geometry variant ndim={ndim} n_el={n_el} p={p} geometry={geo} prec={prec}")
+    from oracle.geometry import GeometryBlocks
+    from paper_1712_00403_amd.geometry import GeometryPreconditioner
+    g = (workloads.sine_geometry(ndim) if geo == "sine"
+         else workloads.warped_geometry(ndim, nu=workloads.wavy_viscosity))
+    prob = workloads.taylor_hood_problem(n_el, p, unit_weights=True)
+    pc = GeometryPreconditioner(prob, g, precision=prec)
+    gb = GeometryBlocks(n_el, p, g)
+    facs = [FDFactors(gb.vel_K[k], gb.vel_M[k]) for k in range(ndim)]
+    r = workloads.residuals(50, 2, pc.N)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    z = pc.apply(torch.from_numpy(r).to(dt).cuda())
+    torch.cuda.synchronize()
+    z = z.cpu().numpy().astype(np.float64)
+    for j in range(2):
+        zo = block_apply(facs, gb.pres_M, r[j], pres_scale=gb.pres_scale, vel_scales=gb.vel_scales)
+        for a, b in zip(pc.offsets[:-1], pc.offsets[1:]):
+            err = _rel(z[j, a:b], zo[a:b])
+            assert err < TOL[prec], f"residual {j} block [{a},{b}): rel err {err:.3e}"
+    pc.close()
