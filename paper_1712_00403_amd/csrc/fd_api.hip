@@ -187,9 +187,11 @@ fd_status run_work(int count, const fd_work* work, hipStream_t stream) {
         int b = 0, c = 0;
         size_t sm = 0;
         const bool pre = (units[k].flags & fdk::kPreScale) != 0;
-        // the pipelined family covers the pencil-fast and fused passes; the
-        // contracted-index-fastest passes run faster on family 2 today
-        if (kernel_family >= 3 && mode != 0 && !pre && fdk::v3_plan(prec, mode, units[k].n, units[k].MT, &c, &sm))
+        // the pipelined family (FP64/FP32) loads raw input straight into LDS
+        // and stores raw accumulators, so passes that scale their input or
+        // output run on family 2
+        const bool post = (units[k].flags & fdk::kPostScale) != 0;
+        if (kernel_family >= 3 && !pre && !post && fdk::v3_plan(prec, mode, units[k].n, units[k].MT, &c, &sm))
           group[k] = 3000 + units[k].n;
         else if (kernel_family >= 2 && fdk::v2_plan(prec, mode, units[k].n, units[k].MT, &b, &c, &sm))
           group[k] = 2000 + b;
