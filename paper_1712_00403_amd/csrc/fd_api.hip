@@ -29,6 +29,9 @@ struct fd_plan_s {
   const void* f_bwd[3] = {nullptr, nullptr, nullptr};  // packed U_i
   const void* p_fwd[3] = {nullptr, nullptr, nullptr};  // plain row-major U_i^T
   const void* p_bwd[3] = {nullptr, nullptr, nullptr};  // plain row-major U_i
+  const void* v_fwd[3] = {nullptr, nullptr, nullptr};  // padded U_i^T (pipelined kernels)
+  const void* v_bwd[3] = {nullptr, nullptr, nullptr};  // padded U_i
+  const void* v_snd[3] = {nullptr, nullptr, nullptr};  // padded U_i as second product of the fused pass
   const double* d_dev[3] = {nullptr, nullptr, nullptr};
   double lam_w[3] = {1, 1, 1};                          // weights used for Lambda on device
   const void* scale_dev = nullptr;                      // D^{-1/2}, I/O type
@@ -101,9 +104,12 @@ bool unit_pass(const fd_plan_s* p, const fd_work& wk, int stage, fdk::PassDesc& 
     u.f2 = p->f_bwd[dir];
     u.pf1 = p->p_fwd[dir];
     u.pf2 = p->p_bwd[dir];
+    u.pv1 = p->v_fwd[dir];
+    u.pv2 = p->v_snd[dir];
   } else {
     u.f1 = fwd ? p->f_fwd[dir] : p->f_bwd[dir];
     u.pf1 = fwd ? p->p_fwd[dir] : p->p_bwd[dir];
+    u.pv1 = fwd ? p->v_fwd[dir] : p->v_bwd[dir];
   }
   u.MT = p->MT[dir];
   u.KS = p->KS[dir];
@@ -438,7 +444,7 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
   }
   // Pack U_i^T (forward) and U_i (backward) in fragment order.
   const int ks = fdk::mfma_kstep(p->prec);
-  size_t off[3][2], offp[3][2], offd[3], offs = 0, total = 0;
+  size_t off[3][2], offp[3][2], offv[3][3], offd[3], offs = 0, total = 0;
   auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
   for (int i = 0; i < ndim; ++i) {
     p->MT[i] = (n[i] + 15) / 16;
@@ -449,6 +455,8 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
     const size_t qb = fdk::plain_bytes(n[i], p->prec);
     offp[i][0] = total; total = align(total + qb);
     offp[i][1] = total; total = align(total + qb);
+    const size_t vb = fdk::v3_factor_bytes(n[i], p->prec);
+    for (int j = 0; j < 3; ++j) { offv[i][j] = total; total = align(total + vb); }
     offd[i] = total; total = align(total + sizeof(double) * n[i]);
   }
   const size_t eb = io_is_f64(p->prec) ? 8 : 4;
@@ -464,6 +472,11 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
     fdk::pack_factor(m, p->U[i].data(), p->prec, host.data() + off[i][1]);
     fdk::plain_factor(m, Ft.data(), p->prec, host.data() + offp[i][0]);
     fdk::plain_factor(m, p->U[i].data(), p->prec, host.data() + offp[i][1]);
+    if (fdk::v3_factor_bytes(m, p->prec)) {
+      fdk::v3_factor(m, Ft.data(), p->prec, false, host.data() + offv[i][0]);
+      fdk::v3_factor(m, p->U[i].data(), p->prec, false, host.data() + offv[i][1]);
+      fdk::v3_factor(m, p->U[i].data(), p->prec, true, host.data() + offv[i][2]);
+    }
     std::memcpy(host.data() + offd[i], dl[i].data(), sizeof(double) * m);
   }
   if (diag_target) {
@@ -491,6 +504,11 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
     p->f_bwd[i] = base + off[i][1];
     p->p_fwd[i] = base + offp[i][0];
     p->p_bwd[i] = base + offp[i][1];
+    if (fdk::v3_factor_bytes(n[i], p->prec)) {
+      p->v_fwd[i] = base + offv[i][0];
+      p->v_bwd[i] = base + offv[i][1];
+      p->v_snd[i] = base + offv[i][2];
+    }
     p->d_dev[i] = reinterpret_cast<const double*>(base + offd[i]);
   }
   if (diag_target) p->scale_dev = base + offs;

@@ -33,6 +33,8 @@ struct PassDesc {
   const void* f2;       // packed factor fragments of the second product (fused pass)
   const void* pf1;      // plain row-major factor (LDS-resident kernels), hi then lo plane
   const void* pf2;      // plain row-major factor of the second product
+  const void* pv1;      // padded row-major factor (pipelined kernels; FP64/FP32 plans)
+  const void* pv2;      // padded factor of the second product (FP32: columns permuted)
   const void* scale;    // pre/post scale vector (N entries, I/O type)
   const double* d[3];   // eigenvalues per direction (fused pass)
   double w[3];          // direction weights (fused pass)
@@ -71,6 +73,14 @@ hipError_t launch_pass3(const PassArgs& args, int prec, int mode, int mt, size_t
 // Bytes of one plain factor (n x n in the storage type, hi and lo planes for split).
 size_t plain_bytes(int n, int prec);
 void plain_factor(int n, const double* F, int prec, void* dst);
+// Padded factor image of the pipelined kernels (FP64/FP32 plans only):
+// round_up(n, 16) rows of v3_ld(n, prec) = round_up(n, 16) entries,
+// row-major, zero padded.
+// `second` stores the image used as the second product of the fused pass
+// (FP32: within every 16 columns, column 4g + r sits at position 4r + g).
+int v3_ld(int n, int prec);
+size_t v3_factor_bytes(int n, int prec);
+void v3_factor(int n, const double* F, int prec, bool second, void* dst);
 
 // Bytes of one packed factor (fragment order) for order n and precision.
 size_t packed_bytes(int n, int prec);

@@ -101,6 +101,29 @@ size_t plain_bytes(int n, int prec) {
   return (prec == 4 || prec == 5) ? 2 * per : per;
 }
 
+int v3_ld(int n, int prec) {
+  (void)prec;
+  return (n + 15) / 16 * 16;  // = rows: the fused pass contracts over all 16 MT rows
+}
+
+size_t v3_factor_bytes(int n, int prec) {
+  if (prec != 0 && prec != 1) return 0;
+  return size_t((n + 15) / 16 * 16) * v3_ld(n, prec) * (prec == 0 ? 8 : 4);
+}
+
+void v3_factor(int n, const double* F, int prec, bool second, void* dst) {
+  const int ld = v3_ld(n, prec), rows = (n + 15) / 16 * 16;
+  std::memset(dst, 0, v3_factor_bytes(n, prec));
+  for (int r = 0; r < rows && r < n; ++r)
+    for (int c = 0; c < n; ++c) {
+      int pos = c;
+      if (second && prec == 1) pos = (c & ~15) | (4 * (c & 3) + ((c & 15) >> 2));
+      const double v = F[r + size_t(n) * c];
+      if (prec == 0) reinterpret_cast<double*>(dst)[size_t(r) * ld + pos] = v;
+      else reinterpret_cast<float*>(dst)[size_t(r) * ld + pos] = float(v);
+    }
+}
+
 void plain_factor(int n, const double* F, int prec, void* dst) {
   const size_t nn = size_t(n) * n;
   for (int r = 0; r < n; ++r)
