@@ -222,6 +222,21 @@ fd_status fd_apply_batched(int32_t count, const fd_work* work, void* stream);
 fd_status fd_timing_enable(int32_t enable);
 fd_status fd_timing_read(double* ms, int32_t* count);
 
+/* Per-launch times of the last fd_timing_read: while timing is enabled every
+ * kernel launch is also bracketed by two events, and fd_timing_read sums them
+ * per launch class (stage, kernel family, largest factor order n of the
+ * launch, precision). fd_timing_launches copies up to `capacity` classes into
+ * `out` (host array) and stores the number of classes in *n_out. */
+typedef struct fd_launch_time {
+  int32_t stage;   /* 0..4 as above */
+  int32_t family;  /* 3 pipelined LDS GEMM, 2 LDS-resident factor, 1 global factor */
+  int32_t n;       /* largest factor order of the units in the launch */
+  int32_t prec;    /* fd_precision */
+  double ms;       /* summed milliseconds */
+  int32_t count;   /* launches summed */
+} fd_launch_time;
+fd_status fd_timing_launches(int32_t capacity, fd_launch_time* out, int32_t* n_out);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* fd_last_error(void);
 

@@ -47,8 +47,14 @@ struct StageRecord {
   int stage;
   hipEvent_t start, end;
 };
+struct LaunchRecord {
+  int stage, family, n, prec;
+  hipEvent_t start, end;
+};
 bool g_timing = false;
 std::vector<StageRecord> g_records;
+std::vector<LaunchRecord> g_launch_records;
+std::vector<fd_launch_time> g_launch_stats;  // filled by fd_timing_read
 
 fd_status fail(fd_status s, const std::string& msg) {
   g_err = msg;
@@ -227,9 +233,20 @@ fd_status run_work(int count, const fd_work* work, hipStream_t stream) {
         int launch_mt = 1;
         auto flush = [&]() -> fd_status {
           if (args.count == 0) return FD_OK;
+          LaunchRecord lr{stage, fam, max_n, prec, nullptr, nullptr};
+          if (g_timing) {
+            hipError_t e = hipEventCreate(&lr.start);
+            if (e == hipSuccess) e = hipEventCreate(&lr.end);
+            if (e == hipSuccess) e = hipEventRecord(lr.start, stream);
+            if (e != hipSuccess) return hip_fail(e, "timing event");
+          }
           hipError_t e = fam == 3 ? fdk::launch_pass3(args, prec, mode, max_mt, smem, stream)
                        : fam == 2 ? fdk::launch_pass2(args, prec, mode, bucket, smem, stream)
                                   : fdk::launch_pass(args, prec, launch_mt, stream);
+          if (g_timing && e == hipSuccess) {
+            e = hipEventRecord(lr.end, stream);
+            if (e == hipSuccess) g_launch_records.push_back(lr);
+          }
           args.count = 0;
           args.total_tiles = 0;
           launch_mt = 1;
@@ -294,7 +311,33 @@ fd_status fd_timing_read(double* ms, int32_t* count) {
     (void)hipEventDestroy(r.end);
   }
   g_records.clear();
+  g_launch_stats.clear();
+  for (auto& r : g_launch_records) {
+    float t = 0.0f;
+    hipError_t e = hipEventSynchronize(r.end);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, r.start, r.end);
+    if (e != hipSuccess && st == FD_OK) st = hip_fail(e, "fd_timing_read");
+    fd_launch_time* slot = nullptr;
+    for (auto& c : g_launch_stats)
+      if (c.stage == r.stage && c.family == r.family && c.n == r.n && c.prec == r.prec) slot = &c;
+    if (!slot) {
+      g_launch_stats.push_back(fd_launch_time{r.stage, r.family, r.n, r.prec, 0.0, 0});
+      slot = &g_launch_stats.back();
+    }
+    slot->ms += t;
+    slot->count += 1;
+    (void)hipEventDestroy(r.start);
+    (void)hipEventDestroy(r.end);
+  }
+  g_launch_records.clear();
   return st;
+}
+
+fd_status fd_timing_launches(int32_t capacity, fd_launch_time* out, int32_t* n_out) {
+  if (!n_out || (capacity > 0 && !out)) return fail(FD_E_ARG, "fd_timing_launches: NULL output");
+  *n_out = int32_t(g_launch_stats.size());
+  for (int32_t i = 0; i < capacity && i < *n_out; ++i) out[i] = g_launch_stats[size_t(i)];
+  return FD_OK;
 }
 
 fd_status fd_assemble_1d(int32_t n_el, int32_t degree, int32_t regularity, int32_t dirichlet,

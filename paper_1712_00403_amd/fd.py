@@ -23,13 +23,18 @@ STATUS_NAMES = {0: "FD_OK", 1: "FD_E_ARG", 2: "FD_E_NOTSPD", 3: "FD_E_NOMEM", 4:
 EXPORTS = ("fd_assemble_1d", "fd_quadrature_1d", "fd_factor_1d", "fd_geometry_coefficients",
            "fd_separable_factors", "fd_operator_diagonal", "fd_setup", "fd_destroy",
            "fd_plan_size", "fd_plan_device_bytes", "fd_plan_factors", "fd_apply",
-           "fd_apply_batched", "fd_timing_enable", "fd_timing_read", "fd_last_error")
+           "fd_apply_batched", "fd_timing_enable", "fd_timing_read", "fd_timing_launches", "fd_last_error")
 
 
 class FDError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
         self.status = status
+
+
+class FDLaunchTime(ctypes.Structure):
+    _fields_ = [("stage", ctypes.c_int32), ("family", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("ms", ctypes.c_double), ("count", ctypes.c_int32)]
 
 
 class FDWork(ctypes.Structure):
@@ -72,6 +77,8 @@ def lib():
     L.fd_apply_batched.argtypes = [ctypes.c_int32, ctypes.POINTER(FDWork), ctypes.c_void_p]
     L.fd_timing_enable.argtypes = [ctypes.c_int32]
     L.fd_timing_read.argtypes = [c_dp, ctypes.POINTER(ctypes.c_int32)]
+    L.fd_timing_launches.argtypes = [ctypes.c_int32, ctypes.POINTER(FDLaunchTime), ctypes.POINTER(ctypes.c_int32)]
+    L.fd_timing_launches.restype = ctypes.c_int
     for name in ("fd_timing_enable", "fd_timing_read", "fd_assemble_1d", "fd_quadrature_1d", "fd_factor_1d",
                  "fd_geometry_coefficients", "fd_separable_factors", "fd_operator_diagonal", "fd_setup", "fd_destroy",
                  "fd_plan_factors", "fd_apply", "fd_apply_batched"):
@@ -281,3 +288,13 @@ def timing_read():
     cnt = (ctypes.c_int32 * 5)()
     _check(lib().fd_timing_read(ms, cnt))
     return {STAGE_NAMES[i]: (ms[i], cnt[i]) for i in range(5)}
+
+
+def timing_launches():
+    """Per launch class of the last timing_read: list of dicts (stage, family, n, prec, ms, count)."""
+    n = ctypes.c_int32(0)
+    _check(lib().fd_timing_launches(0, None, ctypes.byref(n)))
+    arr = (FDLaunchTime * max(n.value, 1))()
+    _check(lib().fd_timing_launches(n.value, arr, ctypes.byref(n)))
+    return [{"stage": STAGE_NAMES[a.stage], "family": a.family, "n": a.n, "prec": a.prec, "ms": a.ms,
+             "count": a.count} for a in arr[:n.value]]
