@@ -122,13 +122,16 @@ fd_status fd_factor_1d(int32_t n, const double* K, const double* M, double* U, d
  *  jac : host, npts * ndim * ndim, point-major, row-major per point:
  *        jac[(p*ndim + a)*ndim + b] = dG_a / deta_b.
  *  nu  : host, npts viscosity values at the physical points G(eta_p).
- *  C   : host output or NULL, ndim^3 * npts, field-major:
+ *  component: -1 for every C_k, or one k in [0, ndim) (then C holds only
+ *        that matrix, as if k were 0 below).
+ *  C   : host output or NULL, ndim^3 * npts (ndim^2 * npts for one
+ *        component), field-major:
  *        C[((k*ndim + a)*ndim + b)*npts + p] = (C_k)_{ab} at point p.
  *  q_weight: host output or NULL, npts.
  * Errors: FD_E_ARG (ndim not 2 or 3, npts < 1, NULL inputs, a singular
  * Jacobian or nu <= 0 at some point). Host computation only. */
 fd_status fd_geometry_coefficients(int32_t ndim, int64_t npts, const double* jac, const double* nu,
-                                   double* C, double* q_weight);
+                                   int32_t component, double* C, double* q_weight);
 
 /* Separable approximation of the diagonal of one C_k (Appendix):
  * c_jj(eta) ~ tau_j(eta_j) prod_{i != j} mu_i(eta_i) on a tensor grid of
@@ -207,6 +210,47 @@ fd_status fd_apply(fd_plan plan, const void* r, void* z, int32_t nrhs, int64_t l
  * set of launches on `stream`: each pass of Algorithm 1 is one launch over the
  * tiles of every unit. Equivalent to calling fd_apply on each unit. */
 fd_status fd_apply_batched(int32_t count, const fd_work* work, void* stream);
+
+/* ------------------------------------------------------ persistent batch */
+
+/* A prepared batched apply that runs as ONE persistent kernel launch.
+ *
+ * fd_batch_create takes a fixed list of works (as for fd_apply_batched; all
+ * plans of one precision class, every factor order n <= 128) and lays out
+ * the passes of Algorithm 1 of every work stage by stage on the device. Each
+ * fd_batch_apply is then a single launch of a persistent grid (every
+ * workgroup resident) that walks the tiles of each stage and meets at a
+ * grid-wide barrier between stages; a tile runs the pass body of its unit
+ * (factor staged in LDS), so patches of different sizes, degrees and
+ * precisions of one class share the launch. The r and z buffers named in the
+ * works are fixed at creation; their contents may change between applies.
+ *
+ * The grid is one 8-wavefront workgroup per CU. fd_batch_tune chooses the
+ * tile width of every stage (the register-budget default or one 16-pencil
+ * tile per wavefront): greedily stage by stage it times the whole apply
+ * (`reps` launches on `stream`, after one warm-up) with that stage narrow and
+ * keeps the faster width; later applies use the choice (*choice = bit s set
+ * when stage s runs narrow). An untuned batch runs every stage at the
+ * default width. Tuning synchronizes the device.
+ *
+ * Applies of one batch must be ordered (one stream, or synchronized): they
+ * share the barrier counter. A barrier wait is bounded: if the grid cannot be
+ * fully resident (other kernels occupy the device), the waits give up after
+ * seconds, the results are undefined and fd_batch_check reports FD_E_HIP.
+ * fd_batch_check waits for the device and reports that flag (and then
+ * restarts the counter, so the batch can run again). Errors of
+ * create: FD_E_ARG (as fd_apply_batched), FD_E_UNSUPPORTED (mixed precision
+ * classes, n > 128, factor image above LDS), FD_E_NOMEM, FD_E_HIP. */
+typedef struct fd_batch_s* fd_batch;
+fd_status fd_batch_create(int32_t count, const fd_work* work, fd_batch* out);
+fd_status fd_batch_apply(fd_batch batch, void* stream);
+fd_status fd_batch_tune(fd_batch batch, void* stream, int32_t reps, int32_t* choice);
+/* Sets the tile widths directly (a choice from an earlier tune); synchronizes the device. */
+fd_status fd_batch_set_config(fd_batch batch, int32_t config);
+/* Tiles per apply, grid size and configuration (bit s: stage s narrow). */
+fd_status fd_batch_info(fd_batch batch, int64_t* tiles, int32_t* grid, int32_t* config);
+fd_status fd_batch_check(fd_batch batch);
+fd_status fd_batch_destroy(fd_batch batch);
 
 /* ---------------------------------------------------------------- diagnostics */
 

@@ -48,21 +48,21 @@ def coefficient_matrices(J, nu):
     """
     J = np.asarray(J, dtype=np.float64)
     P, d, _ = J.shape
+    Ji = np.linalg.inv(J)                          # per point (library routine on a stack)
+    det = np.abs(np.linalg.det(J))
+    base = Ji @ np.swapaxes(Ji, 1, 2)              # J^{-1} J^{-T}
+    w = (np.asarray(nu, dtype=np.float64) * det)[:, None, None]
     out = np.zeros((d, P, d, d))
-    for p in range(P):
-        Ji = np.linalg.inv(J[p])
-        det = abs(np.linalg.det(J[p]))
-        base = Ji @ Ji.T
-        for k in range(d):
-            Dk = Ji[:, k]
-            out[k, p] = nu[p] * (base + np.outer(Dk, Dk)) * det
+    for k in range(d):
+        Dk = Ji[:, :, k]                           # J^{-1} e_k
+        out[k] = w * (base + Dk[:, :, None] * Dk[:, None, :])
     return out
 
 
 def pressure_weight(J, nu):
     """nu^{-1} |det J| at each point: the weight of the TH pressure mass Q (eq. weighted-pressure-mass)."""
     J = np.asarray(J, dtype=np.float64)
-    return np.array([abs(np.linalg.det(J[p])) / nu[p] for p in range(J.shape[0])])
+    return np.abs(np.linalg.det(J)) / np.asarray(nu, dtype=np.float64)
 
 
 def separable_fit(logc, sweeps=20, tol=1e-12):
@@ -146,7 +146,9 @@ def operator_diagonal(n_el, degree, regularity, dirichlet, npts, coef, order):
     off-diagonal entries included); order 0: [Q]_ii = sum_q w_q c(q) B_i(q)^2
     with ``coef`` of shape (nq_1, .., nq_d). B_i is the tensor product of the
     univariate functions, d_a B_i differentiates the factor of direction a.
-    Returns the diagonal as a vector with i_1 fastest.
+    The sum over the grid is one numpy einsum per (a, b) (the library picks
+    the order of the contraction). Returns the diagonal as a vector with i_1
+    fastest.
     """
     d = len(n_el)
     tabs = _space_tables(n_el, degree, regularity, dirichlet, npts)
@@ -160,12 +162,12 @@ def operator_diagonal(n_el, degree, regularity, dirichlet, npts, coef, order):
         return (dB if da else B) * (dB if db else B) * wts[t][None, :]
 
     if order == 0:
-        D = np.einsum(spec, coef, *[table(t, False, False) for t in range(d)])
+        D = np.einsum(spec, coef, *[table(t, False, False) for t in range(d)], optimize=True)
     else:
         D = 0.0
         for a in range(d):
             for b in range(d):
-                D = D + np.einsum(spec, coef[a, b], *[table(t, t == a, t == b) for t in range(d)])
+                D = D + np.einsum(spec, coef[a, b], *[table(t, t == a, t == b) for t in range(d)], optimize=True)
     return np.reshape(D, -1, order="F")
 
 

@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/fd.h"
@@ -34,9 +35,35 @@ struct fd_plan_s {
   const void* v_snd[3] = {nullptr, nullptr, nullptr};  // padded U_i as second product of the fused pass
   const double* d_dev[3] = {nullptr, nullptr, nullptr};
   double lam_w[3] = {1, 1, 1};                          // weights used for Lambda on device
+  float xs[5] = {1, 1, 1, 1, 1}, qs = 1.0f;             // FP16 range scaling per stage
   const void* scale_dev = nullptr;                      // D^{-1/2}, I/O type
   int MT[3] = {0, 0, 0}, KS[3] = {0, 0, 0};
   int device = 0;
+};
+
+struct fd_batch_s {
+  int device = 0;
+  int prec = 0;
+  std::vector<fd_work> works;
+  // per tile width (0: register-budget default, 1: narrow) the passes of each
+  // stage as descriptors and body segments (stage-local indices)
+  struct Layout {
+    std::vector<fdk::BatchDesc> desc[5];
+    std::vector<fdk::BatchSeg> seg[5];
+    int64_t tiles[5] = {0, 0, 0, 0, 0};
+  } lay[2];
+  int width[5] = {0, 0, 0, 0, 0};  // tile width chosen per stage
+  int stage_seg[6] = {0, 0, 0, 0, 0, 0};
+  int64_t max_tiles = 0;
+  size_t smem = 0;
+  int last_stage = -1;
+  int phases = 0;         // barrier phases per launch
+  void* dev = nullptr;    // descriptors and segments of the current widths
+  size_t dev_cap = 0;
+  void* ctl = nullptr;    // barrier counter and error flag
+  uint32_t arrivals = 0;  // barrier arrivals counted so far
+  int cus = 0;
+  bool tuned = false;
 };
 
 namespace {
@@ -117,6 +144,9 @@ bool unit_pass(const fd_plan_s* p, const fd_work& wk, int stage, fdk::PassDesc& 
     u.pf1 = fwd ? p->p_fwd[dir] : p->p_bwd[dir];
     u.pv1 = fwd ? p->v_fwd[dir] : p->v_bwd[dir];
   }
+  u.xscale = p->xs[stage];
+  u.qscale = fused ? p->qs : 1.0f;
+  u.oscale = 1.0f / (u.xscale * u.qscale);
   u.MT = p->MT[dir];
   u.KS = p->KS[dir];
   u.lam_ndim = p->ndim;
@@ -282,6 +312,129 @@ fd_status run_work(int count, const fd_work* work, hipStream_t stream) {
   return FD_OK;
 }
 
+// ---------------------------------------------------------------- persistent batch
+
+static fd_status batch_build_layout(fd_batch_s* b, int narrow) {
+  auto& L = b->lay[narrow];
+  for (int stage = 0; stage < kStages; ++stage) {
+    auto& D = L.desc[stage];
+    auto& S = L.seg[stage];
+    D.clear();
+    S.clear();
+    // passes of this stage, grouped by body (mode, even row tiles, scaling)
+    std::vector<fdk::BatchDesc> passes;
+    for (const fd_work& wk : b->works) {
+      fdk::PassDesc u;
+      if (wk.nrhs == 0 || !unit_pass(wk.plan, wk, stage, u)) continue;
+      fdk::BatchDesc bd{};
+      bd.u = u;
+      bd.mode = stage_mode(u);
+      bd.mt = fdk::batch_mt(b->prec, u.MT);
+      bd.scale = (u.flags & fdk::kPreScale) ? 1 : (u.flags & fdk::kPostScale) ? 2 : 0;
+      const int chunk = fdk::batch_chunk(b->prec, bd.mode, u.MT, narrow);
+      const int64_t NQ = int64_t(u.A) * u.B;
+      bd.u.tiles_per_rhs = int32_t((NQ + chunk - 1) / chunk);
+      b->smem = std::max(b->smem, fdk::batch_lds_bytes(b->prec, u.n, bd.mode == 2));
+      passes.push_back(bd);
+    }
+    std::stable_sort(passes.begin(), passes.end(), [](const fdk::BatchDesc& x, const fdk::BatchDesc& y) {
+      return std::make_tuple(x.mode, x.mt, x.scale) < std::make_tuple(y.mode, y.mt, y.scale);
+    });
+    int64_t t = 0;
+    for (fdk::BatchDesc& bd : passes) {
+      if (S.empty() || S.back().mode != bd.mode || S.back().mt != bd.mt || S.back().scale != bd.scale) {
+        fdk::BatchSeg sg{};
+        sg.d0 = int(D.size());
+        sg.t0 = int(t);
+        sg.mode = bd.mode;
+        sg.mt = bd.mt;
+        sg.scale = bd.scale;
+        sg.narrow = narrow;
+        S.push_back(sg);
+      }
+      bd.u.tile_begin = t;
+      t += int64_t(bd.u.tiles_per_rhs) * bd.u.nrhs;
+      if (t > 0x7fffffffLL) return fail(FD_E_ARG, "fd_batch_create: too many tiles in one stage");
+      D.push_back(bd);
+      S.back().d1 = int(D.size());
+      S.back().t1 = int(t);
+    }
+    L.tiles[stage] = t;
+  }
+  return FD_OK;
+}
+
+// Uploads the descriptors and segments of the chosen tile width of every stage.
+static fd_status batch_upload(fd_batch_s* b) {
+  std::vector<fdk::BatchDesc> desc;
+  std::vector<fdk::BatchSeg> seg;
+  b->max_tiles = 0;
+  for (int st = 0; st < kStages; ++st) {
+    const auto& L = b->lay[b->width[st]];
+    b->stage_seg[st] = int(seg.size());
+    const int base = int(desc.size());
+    for (fdk::BatchSeg sg : L.seg[st]) {
+      sg.d0 += base;
+      sg.d1 += base;
+      seg.push_back(sg);
+    }
+    desc.insert(desc.end(), L.desc[st].begin(), L.desc[st].end());
+    b->max_tiles = std::max(b->max_tiles, L.tiles[st]);
+  }
+  b->stage_seg[kStages] = int(seg.size());
+  const size_t db = desc.size() * sizeof(fdk::BatchDesc), sb = seg.size() * sizeof(fdk::BatchSeg);
+  if (db + sb > b->dev_cap) {
+    if (b->dev) (void)hipFree(b->dev);
+    b->dev = nullptr;
+    b->dev_cap = 0;
+    hipError_t e = hipMalloc(&b->dev, db + sb + 256);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(FD_E_NOMEM, "fd_batch") : hip_fail(e, "hipMalloc");
+    b->dev_cap = db + sb + 256;
+  }
+  // the device may still run an apply that reads the old tables
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(b->dev, desc.data(), db, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(static_cast<unsigned char*>(b->dev) + db, seg.data(), sb, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  return FD_OK;
+}
+
+static fd_status batch_launch(fd_batch_s* b, hipStream_t stream) {
+  if (b->max_tiles == 0) return FD_OK;
+  // one 8-wavefront workgroup per CU: the pass bodies are called functions
+  // with a stack, and the scratch the runtime grants is sized for that
+  const int64_t grid = std::min<int64_t>(b->cus, b->max_tiles);
+  uint32_t* bar = static_cast<uint32_t*>(b->ctl);
+  int32_t* err = reinterpret_cast<int32_t*>(static_cast<unsigned char*>(b->ctl) + 128);
+  // the arrival counter only grows: restart it before it could wrap
+  if (uint64_t(b->arrivals) + uint64_t(b->phases) * uint64_t(grid) >= 0x80000000ull) {
+    hipError_t e = fdk::batch_reset(bar, err, stream);
+    if (e != hipSuccess) return hip_fail(e, "batch reset");
+    b->arrivals = 0;
+  }
+  fdk::BatchArgs a{};
+  size_t nd = 0;
+  for (int st = 0; st < kStages; ++st) nd += b->lay[b->width[st]].desc[st].size();
+  unsigned char* base = static_cast<unsigned char*>(b->dev);
+  a.desc = reinterpret_cast<const fdk::BatchDesc*>(base);
+  a.seg = reinterpret_cast<const fdk::BatchSeg*>(base + nd * sizeof(fdk::BatchDesc));
+  a.barrier = bar;
+  a.error = err;
+  a.base = b->arrivals;
+  for (int i = 0; i <= kStages; ++i) a.stage_seg[i] = b->stage_seg[i];
+  a.last_stage = b->last_stage;
+  hipError_t e = fdk::batch_launch(a, b->prec, int(grid), b->smem, stream);
+  if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
+  b->arrivals += uint32_t(b->phases) * uint32_t(grid);  // every workgroup passes each barrier once
+  return FD_OK;
+}
+
+static int batch_config(const fd_batch_s* b) {
+  int c = 0;
+  for (int st = 0; st < kStages; ++st) c |= b->width[st] << st;
+  return c;
+}
+
 }  // namespace
 
 extern "C" {
@@ -358,8 +511,8 @@ fd_status fd_quadrature_1d(int32_t n_el, int32_t npts, double* x, double* w) {
 }
 
 fd_status fd_geometry_coefficients(int32_t ndim, int64_t npts, const double* jac, const double* nu,
-                                   double* C, double* q_weight) {
-  const int rc = fdh::geometry_coefficients(ndim, npts, jac, nu, C, q_weight);
+                                   int32_t component, double* C, double* q_weight) {
+  const int rc = fdh::geometry_coefficients(ndim, npts, jac, nu, component, C, q_weight);
   if (rc == 1) return fail(FD_E_ARG, "fd_geometry_coefficients: bad arguments");
   if (rc == 2) return fail(FD_E_ARG, "fd_geometry_coefficients: singular Jacobian or nu <= 0");
   return FD_OK;
@@ -485,6 +638,58 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
     }
     (void)n3;
   }
+  // FP16 range (largest finite 65504): each pass converts its FP32 input to
+  // FP16, so the input of every pass is scaled by a power of two that brings
+  // its expected RMS to 1, and the result is scaled back (exact). The RMS
+  // model assumes residual entries of RMS 1 (times D^{-1/2} when scaled): a
+  // product by U_i multiplies the RMS by ||U_i||_F / sqrt(n_i), the division
+  // by Lambda by the RMS of 1 / Lambda (estimated on 4096 fixed multi-indices).
+  if (p->prec == FD_F16 || p->prec == FD_F16_SPLIT) {
+    double gain[3] = {1, 1, 1};
+    for (int i = 0; i < ndim; ++i) {
+      double f = 0.0;
+      for (double v : p->U[i]) f += v * v;
+      gain[i] = std::sqrt(f / n[i]);
+    }
+    double r0 = 1.0;
+    if (diag_target) {
+      double ss = 0.0;
+      for (double v : scale) ss += v * v;
+      r0 = std::sqrt(ss / double(p->N));
+    }
+    double inv_lam = 1.0;
+    if (!p->mass_only) {
+      uint64_t st = 0x9E3779B97F4A7C15ull;
+      double acc2 = 0.0;
+      for (int t = 0; t < 4096; ++t) {
+        double lam = 0.0;
+        for (int i = 0; i < ndim; ++i) {
+          st = st * 6364136223846793005ull + 1442695040888963407ull;
+          lam += p->lam_w[i] * dl[i][(st >> 33) % uint64_t(n[i])];
+        }
+        acc2 += 1.0 / (lam * lam);
+      }
+      inv_lam = std::sqrt(acc2 / 4096.0);
+    }
+    auto pow2 = [](double rms) { return float(std::ldexp(1.0, -int(std::lround(std::log2(rms))))); };
+    const int last = ndim - 1;
+    double in = r0;
+    for (int i = 0; i < last; ++i) {  // forward passes before the fused one
+      p->xs[i] = pow2(in);
+      in *= gain[i];
+    }
+    const int fused_stage = 2;  // 3D: stages 0, 1 then 2; 2D: stage 0 then 2
+    p->xs[fused_stage] = pow2(in);
+    p->qs = pow2(in * p->xs[fused_stage] * gain[last] * inv_lam);
+    double q = in * gain[last] * inv_lam;  // unscaled RMS after the division
+    double back = q * gain[last];
+    if (ndim == 3) {
+      p->xs[3] = pow2(back);
+      back *= gain[1];
+    }
+    p->xs[4] = pow2(back);
+    if (ndim == 2) p->xs[0] = pow2(r0);
+  }
   // Pack U_i^T (forward) and U_i (backward) in fragment order.
   const int ks = fdk::mfma_kstep(p->prec);
   size_t off[3][2], offp[3][2], offv[3][3], offd[3], offs = 0, total = 0;
@@ -592,6 +797,151 @@ fd_status fd_apply(fd_plan plan, const void* r, void* z, int32_t nrhs, int64_t l
   wk.nrhs = nrhs;
   wk.ld = ld;
   return run_work(1, &wk, static_cast<hipStream_t>(stream));
+}
+
+fd_status fd_batch_create(int32_t count, const fd_work* work, fd_batch* out) {
+  if (!out || count < 1 || !work) return fail(FD_E_ARG, "fd_batch_create: bad arguments");
+  *out = nullptr;
+  for (int i = 0; i < count; ++i) {
+    fd_status s = validate_work(work[i]);
+    if (s != FD_OK) return s;
+    for (int d = 0; d < work[i].plan->ndim; ++d)
+      if (work[i].plan->n[d] > 16 * fdk::kBatchMaxMT)
+        return fail(FD_E_UNSUPPORTED, "fd_batch_create: factor order above 128 (use fd_apply_batched)");
+    if (work[i].plan->prec != work[0].plan->prec)
+      return fail(FD_E_UNSUPPORTED, "fd_batch_create: plans of different precision classes");
+  }
+  auto* b = new fd_batch_s;
+  b->prec = work[0].plan->prec;
+  b->works.assign(work, work + count);
+  hipError_t e = hipGetDevice(&b->device);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, b->device);
+  if (e != hipSuccess) {
+    delete b;
+    return hip_fail(e, "fd_batch_create");
+  }
+  fd_status s = FD_OK;
+  for (int narrow = 0; narrow < 2 && s == FD_OK; ++narrow) s = batch_build_layout(b, narrow);
+  if (s == FD_OK && b->smem > 160 * 1024) s = fail(FD_E_UNSUPPORTED, "fd_batch_create: factor image exceeds LDS");
+  int per_cu = 0;
+  if (s == FD_OK) {
+    e = fdk::batch_resident(b->prec, b->smem, &per_cu);
+    if (e != hipSuccess) s = hip_fail(e, "batch occupancy");
+    else if (per_cu < 1) s = fail(FD_E_UNSUPPORTED, "fd_batch_create: batch kernel does not fit a CU");
+  }
+  if (s == FD_OK) {
+    for (int st = 0; st < kStages; ++st)
+      if (b->lay[0].tiles[st] > 0) b->last_stage = st;
+    for (int st = 0; st < b->last_stage; ++st)
+      if (b->lay[0].tiles[st] > 0) ++b->phases;
+    s = batch_upload(b);
+  }
+  if (s == FD_OK) {
+    e = hipMalloc(&b->ctl, 256);
+    if (e == hipSuccess) e = hipMemset(b->ctl, 0, 256);
+    if (e != hipSuccess) s = hip_fail(e, "fd_batch_create");
+  }
+  if (s != FD_OK) {
+    fd_batch_destroy(b);
+    return s;
+  }
+  *out = b;
+  return FD_OK;
+}
+
+fd_status fd_batch_apply(fd_batch b, void* stream) {
+  if (!b) return fail(FD_E_ARG, "fd_batch_apply: NULL batch");
+  return batch_launch(b, static_cast<hipStream_t>(stream));
+}
+
+fd_status fd_batch_tune(fd_batch b, void* stream, int32_t reps, int32_t* choice) {
+  if (!b || reps < 1) return fail(FD_E_ARG, "fd_batch_tune: bad arguments");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) return hip_fail(e, "fd_batch_tune");
+  auto time_current = [&](float* ms) -> fd_status {
+    fd_status s = batch_launch(b, st);  // warm-up
+    hipError_t er = hipEventRecord(e0, st);
+    for (int r = 0; r < reps && s == FD_OK && er == hipSuccess; ++r) s = batch_launch(b, st);
+    if (er == hipSuccess) er = hipEventRecord(e1, st);
+    if (er == hipSuccess) er = hipEventSynchronize(e1);
+    if (er == hipSuccess) er = hipEventElapsedTime(ms, e0, e1);
+    if (s == FD_OK && er != hipSuccess) s = hip_fail(er, "fd_batch_tune");
+    if (s == FD_OK) s = fd_batch_check(b);
+    return s;
+  };
+  // greedy over stages: each stage keeps the tile width that made the whole
+  // apply faster, given the widths already chosen for the earlier stages
+  for (int i = 0; i < kStages; ++i) b->width[i] = 0;
+  fd_status s = batch_upload(b);
+  float best = 0.0f;
+  if (s == FD_OK) s = time_current(&best);
+  for (int stage = 0; stage < kStages && s == FD_OK; ++stage) {
+    if (b->lay[1].tiles[stage] == 0) continue;
+    b->width[stage] = 1;
+    s = batch_upload(b);
+    float ms = 0.0f;
+    if (s == FD_OK) s = time_current(&ms);
+    if (s == FD_OK && ms < best) {
+      best = ms;
+    } else {
+      b->width[stage] = 0;
+    }
+  }
+  if (s == FD_OK) s = batch_upload(b);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s != FD_OK) return s;
+  b->tuned = true;
+  if (choice) *choice = batch_config(b);
+  return FD_OK;
+}
+
+fd_status fd_batch_set_config(fd_batch b, int32_t config) {
+  if (!b || config < 0 || config >= (1 << kStages)) return fail(FD_E_ARG, "fd_batch_set_config: bad arguments");
+  for (int st = 0; st < kStages; ++st) b->width[st] = (config >> st) & 1;
+  return batch_upload(b);
+}
+
+fd_status fd_batch_info(fd_batch b, int64_t* tiles, int32_t* grid, int32_t* config) {
+  if (!b) return fail(FD_E_ARG, "fd_batch_info: NULL batch");
+  if (tiles) {
+    int64_t t = 0;
+    for (int st = 0; st < kStages; ++st) t += b->lay[b->width[st]].tiles[st];
+    *tiles = t;
+  }
+  if (grid) *grid = int32_t(std::min<int64_t>(b->cus, b->max_tiles));
+  if (config) *config = batch_config(b);
+  return FD_OK;
+}
+
+fd_status fd_batch_check(fd_batch b) {
+  if (!b) return fail(FD_E_ARG, "fd_batch_check: NULL batch");
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "fd_batch_check");
+  int32_t flag = 0;
+  e = hipMemcpy(&flag, static_cast<unsigned char*>(b->ctl) + 128, sizeof(flag), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "fd_batch_check");
+  if (flag) {
+    // restart the counter so that the batch can run again
+    uint32_t* bar = static_cast<uint32_t*>(b->ctl);
+    int32_t* err = reinterpret_cast<int32_t*>(static_cast<unsigned char*>(b->ctl) + 128);
+    e = fdk::batch_reset(bar, err, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    b->arrivals = 0;
+    return fail(FD_E_HIP, "fd_batch_apply: a grid barrier wait gave up (grid not fully resident)");
+  }
+  return FD_OK;
+}
+
+fd_status fd_batch_destroy(fd_batch b) {
+  if (!b) return FD_OK;
+  if (b->dev) (void)hipFree(b->dev);
+  if (b->ctl) (void)hipFree(b->ctl);
+  delete b;
+  return FD_OK;
 }
 
 fd_status fd_apply_batched(int32_t count, const fd_work* work, void* stream) {

@@ -1,0 +1,9 @@
+// Batched persistent kernel instantiated for precision class 3 (f16).
+#include "fd_pass.inc"
+#include "fd_pass2.inc"
+#include "fd_batch.inc"
+
+namespace fdk {
+template hipError_t batch_launch_p<3>(const BatchArgs&, int, size_t, hipStream_t);
+template hipError_t batch_resident_p<3>(size_t, int*);
+}  // namespace fdk

@@ -3,6 +3,7 @@
 // diagonal entries, and the diagonals of the Galerkin operators that the
 // diagonal scalings D_V and D_Q restore.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <limits>
@@ -45,11 +46,11 @@ void parallel_for(int64_t count, F body) {
 // C_k = nu (J^{-1} J^{-T} + D_k D_k^T) |det J| with D_k = J^{-1} e_k
 // (Sec. 3, eq. Q_TH) and the pressure-mass weight nu^{-1} |det J|
 // (eq. weighted-pressure-mass), point by point.
-int geometry_coefficients(int d, int64_t P, const double* jac, const double* nu, double* C,
+int geometry_coefficients(int d, int64_t P, const double* jac, const double* nu, int component, double* C,
                           double* qw) {
-  if ((d != 2 && d != 3) || P < 1 || !jac || !nu || (!C && !qw)) return 1;
-  int bad = 0;
-  std::vector<int> bad_chunk(size_t(host_threads()) + 1, 0);
+  if ((d != 2 && d != 3) || P < 1 || !jac || !nu || (!C && !qw) || component < -1 || component >= d) return 1;
+  const int k0 = component < 0 ? 0 : component, k1 = component < 0 ? d : component + 1;
+  std::atomic<int> bad{0};
   parallel_for(P, [&](int64_t lo, int64_t hi) {
     int local_bad = 0;
     for (int64_t p = lo; p < hi; ++p) {
@@ -89,15 +90,15 @@ int geometry_coefficients(int d, int64_t P, const double* jac, const double* nu,
         for (int b = 0; b < d; ++b) {
           double g = 0.0;  // (J^{-1} J^{-T})_{ab}
           for (int c = 0; c < d; ++c) g += inv[a * d + c] * inv[b * d + c];
-          for (int k = 0; k < d; ++k) {
+          for (int k = k0; k < k1; ++k) {
             const double dk = inv[a * d + k] * inv[b * d + k];  // (D_k D_k^T)_{ab}
-            C[((int64_t(k) * d + a) * d + b) * P + p] = v * (g + dk) * adet;
+            C[((int64_t(k - k0) * d + a) * d + b) * P + p] = v * (g + dk) * adet;
           }
         }
     }
-    if (local_bad) bad = 1;  // benign race: any writer stores 1
+    if (local_bad) bad.store(1);
   });
-  return bad ? 2 : 0;
+  return bad.load() ? 2 : 0;
 }
 
 // Diliberto-Straus alternating midrange fit of one field (log values) on a

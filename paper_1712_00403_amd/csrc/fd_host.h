@@ -35,7 +35,8 @@ int basis_tables(int n_el, int degree, int regularity, int dirichlet, int npts, 
 // Coefficient matrices C_k of the velocity blocks and the pressure-mass
 // weight at P points (fd_geometry_coefficients). 0, 1 (arguments) or
 // 2 (singular Jacobian or nu <= 0 at some point).
-int geometry_coefficients(int d, int64_t P, const double* jac, const double* nu, double* C, double* qw);
+int geometry_coefficients(int d, int64_t P, const double* jac, const double* nu, int component, double* C,
+                          double* qw);
 
 // Separable factors of the d diagonal entries of one C_k (fd_separable_factors).
 // 0, 1 (arguments) or 2 (an entry <= 0).

@@ -36,6 +36,10 @@ struct PassDesc {
   const void* pv1;      // padded row-major factor (pipelined kernels; FP64/FP32 plans)
   const void* pv2;      // padded factor of the second product (FP32: columns permuted)
   const void* scale;    // pre/post scale vector (N entries, I/O type)
+  // FP16 range scaling (powers of two, 1 for the other classes): the input is
+  // multiplied by xscale before its conversion to FP16, the fused pass's
+  // second operand by qscale, the FP32 result by oscale = 1 / (xscale qscale)
+  float xscale, qscale, oscale;
   const double* d[3];   // eigenvalues per direction (fused pass)
   double w[3];          // direction weights (fused pass)
   int64_t ld;           // elements between residual vectors
@@ -47,6 +51,35 @@ struct PassDesc {
   int32_t lam_ndim;     // 2 or 3: how a pencil index splits into direction indices
   int32_t n1;           // first direction size (3D fused pass: a = i1 + n1*i2)
   int32_t tiles_per_rhs;
+};
+
+// ---- one persistent launch per batched apply (fd_batch.inc)
+constexpr int kBatchMaxMT = 8;             // factor order n <= 128
+constexpr uint32_t kBatchSpin = 1u << 22;  // about a second of s_sleep per barrier wait
+
+struct BatchDesc {
+  PassDesc u;        // u.tile_begin: first tile of this pass within its stage
+  int32_t mode;      // 0 contract-fast, 1 pencil-fast, 2 fused
+  int32_t mt;        // row tiles of the body (v2_mt of the factor's tiles)
+  int32_t scale;     // 0 none, 1 scale on load, 2 scale on store (mode 0 only)
+  int32_t pad;
+};
+
+// Descriptors [d0, d1) of one stage that share one body (mode, mt, scale);
+// their tiles are [t0, t1) of the stage.
+struct BatchSeg {
+  int32_t d0, d1, t0, t1;
+  int32_t mode, mt, scale, narrow;  // narrow: one 16-pencil tile per wavefront
+};
+
+struct BatchArgs {
+  const BatchDesc* desc;   // ordered by stage, then body, then tile_begin
+  const BatchSeg* seg;     // ordered by stage
+  uint32_t* barrier;       // arrival counter
+  int32_t* error;          // set to 1 if a barrier wait gave up
+  uint32_t base;           // arrivals counted by earlier launches of this batch
+  int32_t stage_seg[6];    // segments of stage s: [stage_seg[s], stage_seg[s+1])
+  int32_t last_stage;      // last stage with tiles (no barrier after it)
 };
 
 struct PassArgs {
@@ -71,6 +104,16 @@ hipError_t launch_pass2(const PassArgs& args, int prec, int mode, int bucket, si
 bool v3_plan(int prec, int mode, int max_n, int mt, int* chunk, size_t* smem);
 hipError_t launch_pass3(const PassArgs& args, int prec, int mode, int mt, size_t smem, hipStream_t stream);
 // Bytes of one plain factor (n x n in the storage type, hi and lo planes for split).
+// Batched persistent launch: pencils per tile and LDS bytes of a pass body,
+// resident workgroups per CU, launch, counter reset.
+// `narrow`: one pencil tile per wavefront instead of the register-budget default.
+int batch_chunk(int prec, int mode, int mt, int narrow);
+int batch_mt(int prec, int mt);
+size_t batch_lds_bytes(int prec, int n, bool fused);
+hipError_t batch_resident(int prec, size_t smem, int* per_cu);
+hipError_t batch_launch(const BatchArgs& args, int prec, int grid, size_t smem, hipStream_t stream);
+hipError_t batch_reset(uint32_t* barrier, int32_t* error, hipStream_t stream);
+
 size_t plain_bytes(int n, int prec);
 void plain_factor(int n, const double* F, int prec, void* dst);
 // Padded factor image of the pipelined kernels (FP64/FP32 plans only):

@@ -96,6 +96,88 @@ hipError_t launch_pass2(const PassArgs& args, int prec, int mode, int bucket, si
   }
 }
 
+// ---------------------------------------------------------------- batched launch
+template <int P> hipError_t batch_launch_p(const BatchArgs&, int, size_t, hipStream_t);
+template <int P> hipError_t batch_resident_p(size_t, int*);
+extern template hipError_t batch_launch_p<0>(const BatchArgs&, int, size_t, hipStream_t);
+extern template hipError_t batch_launch_p<1>(const BatchArgs&, int, size_t, hipStream_t);
+extern template hipError_t batch_launch_p<2>(const BatchArgs&, int, size_t, hipStream_t);
+extern template hipError_t batch_launch_p<3>(const BatchArgs&, int, size_t, hipStream_t);
+extern template hipError_t batch_launch_p<4>(const BatchArgs&, int, size_t, hipStream_t);
+extern template hipError_t batch_launch_p<5>(const BatchArgs&, int, size_t, hipStream_t);
+extern template hipError_t batch_resident_p<0>(size_t, int*);
+extern template hipError_t batch_resident_p<1>(size_t, int*);
+extern template hipError_t batch_resident_p<2>(size_t, int*);
+extern template hipError_t batch_resident_p<3>(size_t, int*);
+extern template hipError_t batch_resident_p<4>(size_t, int*);
+extern template hipError_t batch_resident_p<5>(size_t, int*);
+
+int batch_mt(int prec, int mt);
+template <int P> static int batch_chunk_p(int mode, int mt, int narrow) {
+  return kV2Waves * 16 * (narrow ? 1 : v2_pt<P>(batch_mt(P, mt), mode));
+}
+
+int batch_chunk(int prec, int mode, int mt, int narrow) {
+  switch (prec) {
+    case 0: return batch_chunk_p<0>(mode, mt, narrow);
+    case 1: return batch_chunk_p<1>(mode, mt, narrow);
+    case 2: return batch_chunk_p<2>(mode, mt, narrow);
+    case 3: return batch_chunk_p<3>(mode, mt, narrow);
+    case 4: return batch_chunk_p<4>(mode, mt, narrow);
+    default: return batch_chunk_p<5>(mode, mt, narrow);
+  }
+}
+
+int batch_mt(int prec, int mt) {
+  (void)prec;
+  return (mt + 1) / 2 * 2;
+}
+
+size_t batch_lds_bytes(int prec, int n, bool fused) {
+  switch (prec) {
+    case 0: return v2_lds_bytes<0>(n, fused);
+    case 1: return v2_lds_bytes<1>(n, fused);
+    case 2: return v2_lds_bytes<2>(n, fused);
+    case 3: return v2_lds_bytes<3>(n, fused);
+    case 4: return v2_lds_bytes<4>(n, fused);
+    default: return v2_lds_bytes<5>(n, fused);
+  }
+}
+
+hipError_t batch_resident(int prec, size_t smem, int* per_cu) {
+  switch (prec) {
+    case 0: return batch_resident_p<0>(smem, per_cu);
+    case 1: return batch_resident_p<1>(smem, per_cu);
+    case 2: return batch_resident_p<2>(smem, per_cu);
+    case 3: return batch_resident_p<3>(smem, per_cu);
+    case 4: return batch_resident_p<4>(smem, per_cu);
+    default: return batch_resident_p<5>(smem, per_cu);
+  }
+}
+
+hipError_t batch_launch(const BatchArgs& args, int prec, int grid, size_t smem, hipStream_t stream) {
+  switch (prec) {
+    case 0: return batch_launch_p<0>(args, grid, smem, stream);
+    case 1: return batch_launch_p<1>(args, grid, smem, stream);
+    case 2: return batch_launch_p<2>(args, grid, smem, stream);
+    case 3: return batch_launch_p<3>(args, grid, smem, stream);
+    case 4: return batch_launch_p<4>(args, grid, smem, stream);
+    default: return batch_launch_p<5>(args, grid, smem, stream);
+  }
+}
+
+__global__ void fd_batch_reset_kernel(uint32_t* barrier, int32_t* error) {
+  if (threadIdx.x == 0) {
+    *barrier = 0u;
+    *error = 0;
+  }
+}
+
+hipError_t batch_reset(uint32_t* barrier, int32_t* error, hipStream_t stream) {
+  hipLaunchKernelGGL(fd_batch_reset_kernel, dim3(1), dim3(64), 0, stream, barrier, error);
+  return hipGetLastError();
+}
+
 size_t plain_bytes(int n, int prec) {
   const size_t per = size_t(n) * n * elem_bytes(prec);
   return (prec == 4 || prec == 5) ? 2 * per : per;

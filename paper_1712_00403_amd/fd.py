@@ -23,7 +23,8 @@ STATUS_NAMES = {0: "FD_OK", 1: "FD_E_ARG", 2: "FD_E_NOTSPD", 3: "FD_E_NOMEM", 4:
 EXPORTS = ("fd_assemble_1d", "fd_quadrature_1d", "fd_factor_1d", "fd_geometry_coefficients",
            "fd_separable_factors", "fd_operator_diagonal", "fd_setup", "fd_destroy",
            "fd_plan_size", "fd_plan_device_bytes", "fd_plan_factors", "fd_apply",
-           "fd_apply_batched", "fd_timing_enable", "fd_timing_read", "fd_timing_launches", "fd_last_error")
+           "fd_apply_batched", "fd_batch_create", "fd_batch_apply", "fd_batch_tune", "fd_batch_set_config",
+           "fd_batch_info", "fd_batch_check", "fd_batch_destroy", "fd_timing_enable", "fd_timing_read", "fd_timing_launches", "fd_last_error")
 
 
 class FDError(RuntimeError):
@@ -59,7 +60,7 @@ def lib():
     L.fd_assemble_1d.argtypes = [ctypes.c_int32] * 5 + [c_dp, c_dp, ctypes.POINTER(ctypes.c_int32), c_dp, c_dp]
     L.fd_quadrature_1d.argtypes = [ctypes.c_int32, ctypes.c_int32, c_dp, c_dp]
     L.fd_factor_1d.argtypes = [ctypes.c_int32, c_dp, c_dp, c_dp, c_dp]
-    L.fd_geometry_coefficients.argtypes = [ctypes.c_int32, ctypes.c_int64, c_dp, c_dp, c_dp, c_dp]
+    L.fd_geometry_coefficients.argtypes = [ctypes.c_int32, ctypes.c_int64, c_dp, c_dp, ctypes.c_int32, c_dp, c_dp]
     L.fd_separable_factors.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), c_dp, ctypes.c_int64,
                                        ctypes.c_int32, ctypes.c_double, c_dp, c_dp]
     L.fd_operator_diagonal.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)] + [ctypes.c_int32] * 5 + \
@@ -75,6 +76,18 @@ def lib():
     L.fd_apply.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                            ctypes.c_int64, ctypes.c_void_p]
     L.fd_apply_batched.argtypes = [ctypes.c_int32, ctypes.POINTER(FDWork), ctypes.c_void_p]
+    L.fd_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(FDWork), ctypes.POINTER(ctypes.c_void_p)]
+    L.fd_batch_apply.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    L.fd_batch_tune.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    L.fd_batch_info.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                                ctypes.POINTER(ctypes.c_int32)]
+    L.fd_batch_set_config.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    L.fd_batch_set_config.restype = ctypes.c_int
+    L.fd_batch_check.argtypes = [ctypes.c_void_p]
+    L.fd_batch_destroy.argtypes = [ctypes.c_void_p]
+    for name in ("fd_batch_create", "fd_batch_apply", "fd_batch_tune", "fd_batch_info", "fd_batch_check",
+                 "fd_batch_destroy"):
+        getattr(L, name).restype = ctypes.c_int
     L.fd_timing_enable.argtypes = [ctypes.c_int32]
     L.fd_timing_read.argtypes = [c_dp, ctypes.POINTER(ctypes.c_int32)]
     L.fd_timing_launches.argtypes = [ctypes.c_int32, ctypes.POINTER(FDLaunchTime), ctypes.POINTER(ctypes.c_int32)]
@@ -139,18 +152,23 @@ def factor_1d(K, M):
     return np.ascontiguousarray(U), d
 
 
-def geometry_coefficients(jac, nu, matrices=True):
+def geometry_coefficients(jac, nu, matrices=True, component=None):
     """C (d, d, d, P) with C[k, a, b] = (C_k)_ab at each point, and the pressure weight (P,).
 
     jac: (P, d, d) Jacobians dG_a/deta_b; nu: (P,) viscosity at the mapped points
-    (see fd_geometry_coefficients). ``matrices=False`` returns (None, weight).
+    (see fd_geometry_coefficients). ``matrices=False`` returns (None, weight);
+    ``component=k`` returns C_k alone as (d, d, P).
     """
     jac = _f64c(jac)
     P, d, _ = jac.shape
     nu = _f64c(nu).ravel()
-    C = np.zeros((d, d, d, P)) if matrices else None
-    qw = np.zeros(P)
-    _check(lib().fd_geometry_coefficients(d, P, _dp(jac), _dp(nu), _dp(C), _dp(qw)))
+    if not matrices:
+        C = None
+    else:
+        C = np.empty((d, d, d, P)) if component is None else np.empty((d, d, P))
+    qw = np.empty(P)
+    _check(lib().fd_geometry_coefficients(d, P, _dp(jac), _dp(nu), -1 if component is None else int(component),
+                                          _dp(C), _dp(qw)))
     return C, qw
 
 
@@ -262,8 +280,7 @@ def _stream_handle(stream):
     return stream.cuda_stream
 
 
-def apply_batched(works, stream=None):
-    """works: iterable of (plan, r_ptr, z_ptr, nrhs, ld) -> one fd_apply_batched call."""
+def _work_array(works):
     works = list(works)
     arr = (FDWork * len(works))()
     for i, (plan, r, z, nrhs, ld) in enumerate(works):
@@ -272,7 +289,56 @@ def apply_batched(works, stream=None):
         arr[i].z = z
         arr[i].nrhs = nrhs
         arr[i].ld = ld
-    _check(lib().fd_apply_batched(len(works), arr, _stream_handle(stream)))
+    return arr
+
+
+def apply_batched(works, stream=None):
+    """works: iterable of (plan, r_ptr, z_ptr, nrhs, ld) -> one fd_apply_batched call."""
+    arr = _work_array(works)
+    _check(lib().fd_apply_batched(len(arr), arr, _stream_handle(stream)))
+
+
+class Batch:
+    """A fixed batched apply run as one persistent launch (fd_batch_create / fd_batch_apply)."""
+
+    def __init__(self, works):
+        arr = _work_array(works)
+        h = ctypes.c_void_p(0)
+        _check(lib().fd_batch_create(len(arr), arr, ctypes.byref(h)))
+        self.handle = h.value
+
+    def apply(self, stream=None):
+        _check(lib().fd_batch_apply(self.handle, _stream_handle(stream)))
+
+    def tune(self, stream=None, reps=3):
+        """Choose the tile width of every stage by timing (greedy); returns the bit mask of narrow stages."""
+        c = ctypes.c_int32(0)
+        _check(lib().fd_batch_tune(self.handle, _stream_handle(stream), int(reps), ctypes.byref(c)))
+        return c.value
+
+    def set_config(self, config):
+        _check(lib().fd_batch_set_config(self.handle, int(config)))
+
+    def info(self):
+        t = ctypes.c_int64(0)
+        g = ctypes.c_int32(0)
+        c = ctypes.c_int32(0)
+        _check(lib().fd_batch_info(self.handle, ctypes.byref(t), ctypes.byref(g), ctypes.byref(c)))
+        return {"tiles": t.value, "grid": g.value, "config": c.value}
+
+    def check(self):
+        _check(lib().fd_batch_check(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().fd_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 STAGE_NAMES = ("mode1_fwd", "mode2_fwd", "last_mode_fused", "mode2_bwd", "mode1_bwd")

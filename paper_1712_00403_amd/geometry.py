@@ -32,18 +32,19 @@ def geometry_blocks(problem, geometry, sweeps=20, tol=1e-12):
     v = problem.blocks[0].dirs[0]
     vdeg, vreg, vpts = v.degree, v.regularity, v.degree + 1
     J, nu, nq = _grid(geometry, n_el, vpts)
-    C, _ = fd.geometry_coefficients(J, nu)
-    del J, nu
     out = []
     for k in range(d):
-        tau, mu = fd.separable_factors(C[k], nq, sweeps, tol)
+        # one coefficient matrix at a time keeps the host memory at d^2 fields
+        Ck, _ = fd.geometry_coefficients(J, nu, component=k)
+        tau, mu = fd.separable_factors(Ck, nq, sweeps, tol)
         Ks, Ms = [], []
         for j in range(d):
             Ks.append(fd.assemble_1d(n_el[j], vdeg, vreg, True, vpts, tau=tau[j])[0])
             Ms.append(fd.assemble_1d(n_el[j], vdeg, vreg, True, vpts, mu=mu[j])[1])
-        dA = fd.operator_diagonal(n_el, vdeg, vreg, True, vpts, C[k], 1)
+        dA = fd.operator_diagonal(n_el, vdeg, vreg, True, vpts, Ck, 1)
+        del Ck
         out.append((Ks, Ms, np.ones(d), dA))
-    del C
+    del J, nu
     q = problem.blocks[-1].dirs[0]
     qdeg, qreg, qpts = q.degree, q.regularity, q.degree + 1
     Jq, nuq, _ = _grid(geometry, n_el, qpts)

@@ -57,7 +57,7 @@ CASES_3D = [((3, 4, 5), 2, (2.0, 1.0, 1.0)), ((18, 10, 22), 3, (1.0, 2.0, 1.0)),
             ((8, 33, 5), 1, (1.0, 1.0, 2.0)), ((6, 7, 9), 5, (1.0, 1.0, 1.0))]
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "bf16_split"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "bf16_split", "f16", "f16_split"])
 @pytest.mark.parametrize("n_el,p,w", CASES_3D)
 def test_fd3d_velocity_block(prec, n_el, p, w):
     _case(f"fd3d velocity n_el={n_el} p={p} w={w} prec={prec}")
@@ -72,7 +72,7 @@ def test_fd3d_velocity_block(prec, n_el, p, w):
     plan.close()
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "bf16_split"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "bf16_split", "f16", "f16_split"])
 @pytest.mark.parametrize("n_el,p", [((16, 16), 2), ((13, 29), 3), ((2, 3), 1), ((60, 40), 4)])
 def test_fd2d_velocity_block(prec, n_el, p):
     _case(f"fd2d velocity n_el={n_el} p={p} prec={prec}")
@@ -87,7 +87,7 @@ def test_fd2d_velocity_block(prec, n_el, p):
     plan.close()
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f16"])
 @pytest.mark.parametrize("n_el,p", [((5, 9, 4), 2), ((20, 11, 17), 3), ((7, 12), 2)])
 def test_pressure_mass_block(prec, n_el, p):
     _case(f"pressure mass n_el={n_el} p={p} prec={prec}")
