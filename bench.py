@@ -86,6 +86,9 @@ def main():
                     help="precisions of the 256-patch persistent batch leg ('' to skip)")
     ap.add_argument("--batch-patches", type=int, default=256)
     ap.add_argument("--batch-only", action="store_true", help="run only the persistent batch leg")
+    ap.add_argument("--serve-seconds", type=float, default=8.0, help="length of each serving run (0 to skip)")
+    ap.add_argument("--serve", default="f64,bf16", help="precisions of the serving runs")
+    ap.add_argument("--serve-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -101,6 +104,10 @@ def main():
     if args.batch_only:
         torch.cuda.set_device(0)
         print(json.dumps({"batch_256_patches": bench_batch(args, [p for p in args.batch.split(",") if p])}))
+        return
+    if args.serve_only:
+        torch.cuda.set_device(0)
+        print(json.dumps({"serving": bench_serve(args, [p for p in args.serve.split(",") if p])}))
         return
     cfg = workloads.CONFIGS["c2_3d_64_p3"]
     prob = cfg["problem"]()
@@ -221,6 +228,9 @@ def main():
     batch = None
     if args.batch and not args.only:
         batch = bench_batch(args, [p for p in args.batch.split(",") if p])
+    serving = None
+    if args.serve_seconds > 0 and args.serve and not args.only:
+        serving = bench_serve(args, [p for p in args.serve.split(",") if p])
 
     out = {"metric": METRIC, "value": round(head["applies_per_s"], 3), "unit": "applies/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -231,7 +241,7 @@ def main():
                       "global_batch": nrhs, "dofs_per_residual": N, "parallelism": "single GPU"},
            "dof_per_s": head["dof_per_s"], "rel_err_vs_oracle": head["rel_err_max"],
            "plan_setup_s": round(setup_s, 3), "roofline": roofline, "cpu_baseline": cpu,
-           "ladder": ladder, "batch_256_patches": batch}
+           "ladder": ladder, "batch_256_patches": batch, "serving": serving}
     print(json.dumps(out))
     for pc in pcs.values():
         pc.close()
@@ -344,6 +354,51 @@ def bench_batch(args, precisions):
         for pc in pcs:
             pc.close()
         del R, Z
+        torch.cuda.empty_cache()
+    return out
+
+
+def bench_serve(args, precisions):
+    """Poisson stream of FD-apply requests of mixed sizes through the continuous-batching server.
+
+    2000 requests/s (seed 4): 70% 2D 16x16 p = 2 block vectors, 25% 3D 64^3
+    p = 3, 5% 3D 96^3 p = 4; residuals from a seeded device pool per class;
+    factors cached on the device under an HBM budget; latency = completion
+    (HIP event on the launch stream) minus arrival.
+    """
+    import torch
+
+    from paper_1712_00403_amd import serve, workloads
+    mix = {"2d_16_p2": 0.70, "3d_64_p3": 0.25, "3d_96_p4": 0.05}
+    problems = {"2d_16_p2": lambda: workloads.taylor_hood_problem((16, 16), 2, unit_weights=True),
+                "3d_64_p3": lambda: workloads.taylor_hood_problem((64, 64, 64), 3),
+                "3d_96_p4": lambda: workloads.taylor_hood_problem((96, 96, 96), 4)}
+    out = {"rate_per_s": 2000.0, "seconds": args.serve_seconds, "mix": mix, "precisions": {}}
+    for prec in precisions:
+        classes = {k: serve.RequestClass(k, f, prec) for k, f in problems.items()}
+        arrivals = serve.poisson_arrivals(2000.0, args.serve_seconds, mix, seed=4)
+        ex = serve.GpuExecutor(classes, slots=4, seed=4)
+        srv = serve.Server(classes, ex, hbm_budget=16 << 30)
+        # warm the plan cache and the kernels (untimed)
+        warm = [serve.Request(-1 - i, k, 0.0) for i, k in enumerate(problems)]
+        for r in warm:
+            srv.submit(r)
+        while srv.pending or srv.inflight:
+            srv.step()
+            srv.collect(wait=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ex.t0, ex.ev_ref = t0, None
+        reqs = serve.run_stream(srv, arrivals, lambda: time.perf_counter() - t0, {k: 4 for k in problems})
+        summ = serve.latency_summary(reqs, args.serve_seconds)
+        summ.update({"steps": srv.steps, "plan_cache_bytes": srv.cache.bytes, "evictions": srv.cache.evictions,
+                     "offered_dof_per_s": sum(r.dofs for r in reqs) / args.serve_seconds})
+        out["precisions"][prec] = summ
+        log(f"serving {prec}: {summ['requests']} requests, p50 {summ['p50_ms']:.3f} ms, "
+            f"p99 {summ['p99_ms']:.3f} ms, {summ['dof_per_s'] / 1e9:.2f} GDOF/s, {srv.steps} steps")
+        for pc, _ in srv.cache.entries.values():
+            pc.close()
+        del ex, srv
         torch.cuda.empty_cache()
     return out
 
