@@ -116,9 +116,9 @@ hipError_t batch_reset(uint32_t* barrier, int32_t* error, hipStream_t stream);
 
 size_t plain_bytes(int n, int prec);
 void plain_factor(int n, const double* F, int prec, void* dst);
-// Padded factor image of the pipelined kernels (FP64/FP32 plans only):
-// round_up(n, 16) rows of v3_ld(n, prec) = round_up(n, 16) entries,
-// row-major, zero padded.
+// Padded factor image of the pipelined kernels (FP64, FP32, BF16, FP16
+// plans): v3_ld(n, prec) rows and columns (n rounded up to 16, to 32 for the
+// 16-bit classes), row-major, zero padded.
 // `second` stores the image used as the second product of the fused pass
 // (FP32: within every 16 columns, column 4g + r sits at position 4r + g).
 int v3_ld(int n, int prec);

@@ -45,6 +45,8 @@ template <int P>
 hipError_t launch3_p(const PassArgs& args, int mode, int mt, size_t smem, hipStream_t stream);
 extern template hipError_t launch3_p<0>(const PassArgs&, int, int, size_t, hipStream_t);
 extern template hipError_t launch3_p<1>(const PassArgs&, int, int, size_t, hipStream_t);
+extern template hipError_t launch3_p<2>(const PassArgs&, int, int, size_t, hipStream_t);
+extern template hipError_t launch3_p<3>(const PassArgs&, int, int, size_t, hipStream_t);
 
 template <int P>
 static bool v3_plan_p(int mode, int max_n, int mt, int* chunk, size_t* smem) {
@@ -57,9 +59,13 @@ static bool v3_plan_p(int mode, int max_n, int mt, int* chunk, size_t* smem) {
   return true;
 }
 
+int v3_mt(int prec, int mt) { return prec >= 2 ? (mt + 1) / 2 * 2 : mt; }
+
 bool v3_plan(int prec, int mode, int max_n, int mt, int* chunk, size_t* smem) {
   if (prec == 0) return v3_plan_p<0>(mode, max_n, mt, chunk, smem);
   if (prec == 1) return v3_plan_p<1>(mode, max_n, mt, chunk, smem);
+  if (prec == 2) return v3_plan_p<2>(mode, max_n, v3_mt(prec, mt), chunk, smem);
+  if (prec == 3) return v3_plan_p<3>(mode, max_n, v3_mt(prec, mt), chunk, smem);
   return false;
 }
 
@@ -67,6 +73,8 @@ hipError_t launch_pass3(const PassArgs& args, int prec, int mode, int mt, size_t
   if (args.total_tiles <= 0) return hipSuccess;
   if (prec == 0) return launch3_p<0>(args, mode, mt, smem, stream);
   if (prec == 1) return launch3_p<1>(args, mode, mt, smem, stream);
+  if (prec == 2) return launch3_p<2>(args, mode, v3_mt(prec, mt), smem, stream);
+  if (prec == 3) return launch3_p<3>(args, mode, v3_mt(prec, mt), smem, stream);
   return hipErrorInvalidValue;
 }
 
@@ -184,25 +192,37 @@ size_t plain_bytes(int n, int prec) {
 }
 
 int v3_ld(int n, int prec) {
-  (void)prec;
-  return (n + 15) / 16 * 16;  // = rows: the fused pass contracts over all 16 MT rows
+  // = rows: the fused pass contracts over all 16 MT rows (MT even for 16-bit)
+  const int r = prec >= 2 ? 32 : 16;
+  return (n + r - 1) / r * r;
 }
 
 size_t v3_factor_bytes(int n, int prec) {
-  if (prec != 0 && prec != 1) return 0;
-  return size_t((n + 15) / 16 * 16) * v3_ld(n, prec) * (prec == 0 ? 8 : 4);
+  if (prec < 0 || prec > 3) return 0;
+  const size_t eb = prec == 0 ? 8 : (prec == 1 ? 4 : 2);
+  return size_t(v3_ld(n, prec)) * v3_ld(n, prec) * eb;
 }
 
 void v3_factor(int n, const double* F, int prec, bool second, void* dst) {
-  const int ld = v3_ld(n, prec), rows = (n + 15) / 16 * 16;
+  const int ld = v3_ld(n, prec);
   std::memset(dst, 0, v3_factor_bytes(n, prec));
-  for (int r = 0; r < rows && r < n; ++r)
+  for (int r = 0; r < n; ++r)
     for (int c = 0; c < n; ++c) {
       int pos = c;
+      // second product of the fused pass: the first product's accumulator
+      // registers are the operand, so the columns follow their layout
       if (second && prec == 1) pos = (c & ~15) | (4 * (c & 3) + ((c & 15) >> 2));
+      if (second && prec >= 2) {
+        // within 32 columns: column 4 g + j at 8 g + j, column 16 + 4 g + j at 8 g + 4 + j
+        const int w = c & 31, hi = w >> 4, g = (w & 15) >> 2, j = w & 3;
+        pos = (c & ~31) | (8 * g + 4 * hi + j);
+      }
       const double v = F[r + size_t(n) * c];
-      if (prec == 0) reinterpret_cast<double*>(dst)[size_t(r) * ld + pos] = v;
-      else reinterpret_cast<float*>(dst)[size_t(r) * ld + pos] = float(v);
+      const size_t idx = size_t(r) * ld + pos;
+      if (prec == 0) reinterpret_cast<double*>(dst)[idx] = v;
+      else if (prec == 1) reinterpret_cast<float*>(dst)[idx] = float(v);
+      else if (prec == 2) reinterpret_cast<uint16_t*>(dst)[idx] = to_bf16(float(v));
+      else reinterpret_cast<_Float16*>(dst)[idx] = (_Float16)float(v);
     }
 }
 
