@@ -79,7 +79,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--precisions", default="f64,f32,bf16,bf16_split")
+    ap.add_argument("--precisions", default="f64,f32,bf16,f16,bf16_split,f16_split")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--only", default=None, help="time only this precision (profiling runs)")
     ap.add_argument("--batch", default="bf16,f32",
