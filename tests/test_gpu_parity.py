@@ -256,3 +256,44 @@ def test_geometry_variant_block_apply(prec, ndim, n_el, p, geo):
             err = _rel(z[j, a:b], zo[a:b])
             assert err < TOL[prec], f"residual {j} block [{a},{b}): rel err {err:.3e}"
     pc.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_largest_factor_order_256(prec):
+    """n = 256 (the largest factor order a plan accepts) in direction 1, tiny elsewhere."""
+    _case(f"n=256 direction, prec={prec}")
+    Ks, Ms = _vel_factors((128, 2, 3), 2)
+    assert Ks[0].shape[0] == 256
+    f = FDFactors(Ks, Ms, np.array([1.0, 2.0, 1.0]))
+    plan = _fd().Plan(Ks, Ms, weights=np.array([1.0, 2.0, 1.0]), precision=prec)
+    r = workloads.residuals(18, 2, plan.N)
+    z = _run_plan(plan, r)
+    for j in range(2):
+        assert _rel(z[j], fd_apply(f, r[j])) < TOL[prec]
+    plan.close()
+
+
+def test_smallest_factor_order_2_and_empty_work():
+    """n = 2 (pressure space of one linear element) and nrhs = 0 (a no-op)."""
+    _case("n=2 directions and an empty work")
+    Ms = [pressure_1d(1, 1), pressure_1d(3, 1), pressure_1d(1, 1)]
+    assert [M.shape[0] for M in Ms] == [2, 4, 2]
+    plan = _fd().Plan(None, Ms, precision="f64")
+    r = workloads.residuals(19, 3, plan.N)
+    z = _run_plan(plan, r)
+    for j in range(3):
+        assert _rel(z[j], mass_solve_banded(Ms, r[j])) < TOL["f64"]
+    buf = torch.full((1, plan.N), 7.0, dtype=torch.float64, device="cuda")
+    plan.apply_ptr(buf.data_ptr(), buf.data_ptr(), 0, plan.N, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert torch.all(buf == 7.0)
+    plan.close()
+
+
+def test_plan_rejects_order_above_256():
+    _case("fd_setup argument checks")
+    fd = _fd()
+    Ks, Ms = _vel_factors((129, 2, 2), 2)  # n = 258
+    with pytest.raises(fd.FDError) as e:
+        fd.Plan(Ks, Ms)
+    assert e.value.status == fd.FD_E_ARG
