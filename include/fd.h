@@ -225,13 +225,18 @@ fd_status fd_apply_batched(int32_t count, const fd_work* work, void* stream);
  * precisions of one class share the launch. The r and z buffers named in the
  * works are fixed at creation; their contents may change between applies.
  *
- * The grid is one 8-wavefront workgroup per CU. fd_batch_tune chooses the
- * tile width of every stage (the register-budget default or one 16-pencil
- * tile per wavefront): greedily stage by stage it times the whole apply
- * (`reps` launches on `stream`, after one warm-up) with that stage narrow and
- * keeps the faster width; later applies use the choice (*choice = bit s set
- * when stage s runs narrow). An untuned batch runs every stage at the
- * default width. Tuning synchronizes the device.
+ * The grid is one 8-wavefront workgroup per CU. A stage runs each of its
+ * passes with one of three bodies: 0 wide (factor resident in LDS, the
+ * register-budget tile width), 1 narrow (factor resident in LDS, one 16-pencil
+ * tile per wavefront), 2 pipelined (factor and pencil blocks streamed through
+ * an LDS ring by direct loads; FP64/FP32/BF16/FP16 passes that scale neither
+ * input nor output, the other passes of the stage run wide). The
+ * configuration word holds the choice of stage s in bits 2s and 2s + 1.
+ * fd_batch_tune chooses greedily stage by stage: it times the whole apply
+ * (`reps` launches on `stream`, after one warm-up) with each choice that
+ * changes the stage and keeps the fastest; later applies use the result
+ * (*choice = the configuration word). An untuned batch runs every stage
+ * wide. Tuning synchronizes the device.
  *
  * Applies of one batch must be ordered (one stream, or synchronized): they
  * share the barrier counter. A barrier wait is bounded: if the grid cannot be
@@ -245,9 +250,10 @@ typedef struct fd_batch_s* fd_batch;
 fd_status fd_batch_create(int32_t count, const fd_work* work, fd_batch* out);
 fd_status fd_batch_apply(fd_batch batch, void* stream);
 fd_status fd_batch_tune(fd_batch batch, void* stream, int32_t reps, int32_t* choice);
-/* Sets the tile widths directly (a choice from an earlier tune); synchronizes the device. */
+/* Sets the body choices directly (a configuration word, e.g. from an earlier
+ * tune; a choice of 3 is FD_E_ARG); synchronizes the device. */
 fd_status fd_batch_set_config(fd_batch batch, int32_t config);
-/* Tiles per apply, grid size and configuration (bit s: stage s narrow). */
+/* Tiles per apply, grid size and configuration word. */
 fd_status fd_batch_info(fd_batch batch, int64_t* tiles, int32_t* grid, int32_t* config);
 fd_status fd_batch_check(fd_batch batch);
 fd_status fd_batch_destroy(fd_batch batch);

@@ -45,14 +45,16 @@ struct fd_batch_s {
   int device = 0;
   int prec = 0;
   std::vector<fd_work> works;
-  // per tile width (0: register-budget default, 1: narrow) the passes of each
-  // stage as descriptors and body segments (stage-local indices)
+  // per body choice (kBodyWide, kBodyNarrow, kBodyPipelined: the passes that
+  // have a pipelined body, the others wide) the passes of each stage as
+  // descriptors and body segments (stage-local indices)
   struct Layout {
     std::vector<fdk::BatchDesc> desc[5];
     std::vector<fdk::BatchSeg> seg[5];
     int64_t tiles[5] = {0, 0, 0, 0, 0};
-  } lay[2];
-  int width[5] = {0, 0, 0, 0, 0};  // tile width chosen per stage
+    bool differs[5] = {false, false, false, false, false};  // some pass of the stage runs another body than wide
+  } lay[3];
+  int width[5] = {0, 0, 0, 0, 0};  // body choice per stage
   int stage_seg[6] = {0, 0, 0, 0, 0, 0};
   int64_t max_tiles = 0;
   size_t smem = 0;
@@ -314,42 +316,58 @@ fd_status run_work(int count, const fd_work* work, hipStream_t stream) {
 
 // ---------------------------------------------------------------- persistent batch
 
-static fd_status batch_build_layout(fd_batch_s* b, int narrow) {
-  auto& L = b->lay[narrow];
+static fd_status batch_build_layout(fd_batch_s* b, int choice) {
+  auto& L = b->lay[choice];
   for (int stage = 0; stage < kStages; ++stage) {
     auto& D = L.desc[stage];
     auto& S = L.seg[stage];
     D.clear();
     S.clear();
-    // passes of this stage, grouped by body (mode, even row tiles, scaling)
-    std::vector<fdk::BatchDesc> passes;
+    L.differs[stage] = false;
+    // passes of this stage, grouped by body (kind, mode, row tiles, scaling)
+    std::vector<std::pair<int, fdk::BatchDesc>> passes;  // (body, descriptor)
     for (const fd_work& wk : b->works) {
       fdk::PassDesc u;
       if (wk.nrhs == 0 || !unit_pass(wk.plan, wk, stage, u)) continue;
       fdk::BatchDesc bd{};
       bd.u = u;
       bd.mode = stage_mode(u);
-      bd.mt = fdk::batch_mt(b->prec, u.MT);
       bd.scale = (u.flags & fdk::kPreScale) ? 1 : (u.flags & fdk::kPostScale) ? 2 : 0;
-      const int chunk = fdk::batch_chunk(b->prec, bd.mode, u.MT, narrow);
+      int body = choice == fdk::kBodyNarrow ? fdk::kBodyNarrow : fdk::kBodyWide;
+      int chunk = 0, mt3 = 0;
+      size_t sm3 = 0;
+      // the pipelined body loads raw input straight into LDS and stores raw
+      // accumulators: passes that scale either run an LDS-resident body
+      if (choice == fdk::kBodyPipelined && bd.scale == 0 && u.pv1 &&
+          fdk::batch_plan3(b->prec, bd.mode, u.MT, &mt3, &chunk, &sm3)) {
+        body = fdk::kBodyPipelined;
+        bd.mt = mt3;
+        b->smem = std::max(b->smem, sm3);
+      } else {
+        bd.mt = fdk::batch_mt(b->prec, u.MT);
+        chunk = fdk::batch_chunk(b->prec, bd.mode, u.MT, body == fdk::kBodyNarrow);
+        b->smem = std::max(b->smem, fdk::batch_lds_bytes(b->prec, u.n, bd.mode == 2));
+      }
+      if (body != fdk::kBodyWide) L.differs[stage] = true;
       const int64_t NQ = int64_t(u.A) * u.B;
       bd.u.tiles_per_rhs = int32_t((NQ + chunk - 1) / chunk);
-      b->smem = std::max(b->smem, fdk::batch_lds_bytes(b->prec, u.n, bd.mode == 2));
-      passes.push_back(bd);
+      passes.emplace_back(body, bd);
     }
-    std::stable_sort(passes.begin(), passes.end(), [](const fdk::BatchDesc& x, const fdk::BatchDesc& y) {
-      return std::make_tuple(x.mode, x.mt, x.scale) < std::make_tuple(y.mode, y.mt, y.scale);
-    });
+    auto key = [](const std::pair<int, fdk::BatchDesc>& x) {
+      return std::make_tuple(x.first, x.second.mode, x.second.mt, x.second.scale);
+    };
+    std::stable_sort(passes.begin(), passes.end(), [&](const auto& x, const auto& y) { return key(x) < key(y); });
     int64_t t = 0;
-    for (fdk::BatchDesc& bd : passes) {
-      if (S.empty() || S.back().mode != bd.mode || S.back().mt != bd.mt || S.back().scale != bd.scale) {
+    for (size_t i = 0; i < passes.size(); ++i) {
+      fdk::BatchDesc bd = passes[i].second;
+      if (i == 0 || key(passes[i - 1]) != key(passes[i])) {
         fdk::BatchSeg sg{};
         sg.d0 = int(D.size());
         sg.t0 = int(t);
         sg.mode = bd.mode;
         sg.mt = bd.mt;
         sg.scale = bd.scale;
-        sg.narrow = narrow;
+        sg.body = passes[i].first;
         S.push_back(sg);
       }
       bd.u.tile_begin = t;
@@ -364,7 +382,7 @@ static fd_status batch_build_layout(fd_batch_s* b, int narrow) {
   return FD_OK;
 }
 
-// Uploads the descriptors and segments of the chosen tile width of every stage.
+// Uploads the descriptors and segments of the chosen body of every stage.
 static fd_status batch_upload(fd_batch_s* b) {
   std::vector<fdk::BatchDesc> desc;
   std::vector<fdk::BatchSeg> seg;
@@ -429,9 +447,10 @@ static fd_status batch_launch(fd_batch_s* b, hipStream_t stream) {
   return FD_OK;
 }
 
+// two bits per stage: the body choice of stage s in bits 2s, 2s + 1
 static int batch_config(const fd_batch_s* b) {
   int c = 0;
-  for (int st = 0; st < kStages; ++st) c |= b->width[st] << st;
+  for (int st = 0; st < kStages; ++st) c |= b->width[st] << (2 * st);
   return c;
 }
 
@@ -821,7 +840,7 @@ fd_status fd_batch_create(int32_t count, const fd_work* work, fd_batch* out) {
     return hip_fail(e, "fd_batch_create");
   }
   fd_status s = FD_OK;
-  for (int narrow = 0; narrow < 2 && s == FD_OK; ++narrow) s = batch_build_layout(b, narrow);
+  for (int c = 0; c < 3 && s == FD_OK; ++c) s = batch_build_layout(b, c);
   if (s == FD_OK && b->smem > 160 * 1024) s = fail(FD_E_UNSUPPORTED, "fd_batch_create: factor image exceeds LDS");
   int per_cu = 0;
   if (s == FD_OK) {
@@ -872,23 +891,26 @@ fd_status fd_batch_tune(fd_batch b, void* stream, int32_t reps, int32_t* choice)
     if (s == FD_OK) s = fd_batch_check(b);
     return s;
   };
-  // greedy over stages: each stage keeps the tile width that made the whole
-  // apply faster, given the widths already chosen for the earlier stages
+  // greedy over stages: each stage keeps the body choice that made the whole
+  // apply fastest, given the choices already made for the earlier stages
   for (int i = 0; i < kStages; ++i) b->width[i] = 0;
   fd_status s = batch_upload(b);
   float best = 0.0f;
   if (s == FD_OK) s = time_current(&best);
   for (int stage = 0; stage < kStages && s == FD_OK; ++stage) {
-    if (b->lay[1].tiles[stage] == 0) continue;
-    b->width[stage] = 1;
-    s = batch_upload(b);
-    float ms = 0.0f;
-    if (s == FD_OK) s = time_current(&ms);
-    if (s == FD_OK && ms < best) {
-      best = ms;
-    } else {
-      b->width[stage] = 0;
+    int keep = 0;
+    for (int c = 1; c < 3 && s == FD_OK; ++c) {
+      if (!b->lay[c].differs[stage]) continue;
+      b->width[stage] = c;
+      s = batch_upload(b);
+      float ms = 0.0f;
+      if (s == FD_OK) s = time_current(&ms);
+      if (s == FD_OK && ms < best) {
+        best = ms;
+        keep = c;
+      }
     }
+    b->width[stage] = keep;
   }
   if (s == FD_OK) s = batch_upload(b);
   (void)hipEventDestroy(e0);
@@ -900,8 +922,10 @@ fd_status fd_batch_tune(fd_batch b, void* stream, int32_t reps, int32_t* choice)
 }
 
 fd_status fd_batch_set_config(fd_batch b, int32_t config) {
-  if (!b || config < 0 || config >= (1 << kStages)) return fail(FD_E_ARG, "fd_batch_set_config: bad arguments");
-  for (int st = 0; st < kStages; ++st) b->width[st] = (config >> st) & 1;
+  if (!b || config < 0 || config >= (1 << (2 * kStages))) return fail(FD_E_ARG, "fd_batch_set_config: bad arguments");
+  for (int st = 0; st < kStages; ++st)
+    if (((config >> (2 * st)) & 3) == 3) return fail(FD_E_ARG, "fd_batch_set_config: body choice 3");
+  for (int st = 0; st < kStages; ++st) b->width[st] = (config >> (2 * st)) & 3;
   return batch_upload(b);
 }
 

@@ -60,16 +60,20 @@ constexpr uint32_t kBatchSpin = 1u << 22;  // about a second of s_sleep per barr
 struct BatchDesc {
   PassDesc u;        // u.tile_begin: first tile of this pass within its stage
   int32_t mode;      // 0 contract-fast, 1 pencil-fast, 2 fused
-  int32_t mt;        // row tiles of the body (v2_mt of the factor's tiles)
+  int32_t mt;        // row tiles of the body (batch_mt, or v3_mt for the pipelined body)
   int32_t scale;     // 0 none, 1 scale on load, 2 scale on store (mode 0 only)
   int32_t pad;
 };
 
-// Descriptors [d0, d1) of one stage that share one body (mode, mt, scale);
-// their tiles are [t0, t1) of the stage.
+// Bodies of a batch segment: LDS-resident factor with the register-budget
+// tile width or one 16-pencil tile per wavefront; pipelined LDS ring.
+constexpr int32_t kBodyWide = 0, kBodyNarrow = 1, kBodyPipelined = 2;
+
+// Descriptors [d0, d1) of one stage that share one body (mode, mt, scale,
+// body); their tiles are [t0, t1) of the stage.
 struct BatchSeg {
   int32_t d0, d1, t0, t1;
-  int32_t mode, mt, scale, narrow;  // narrow: one 16-pencil tile per wavefront
+  int32_t mode, mt, scale, body;
 };
 
 struct BatchArgs {
@@ -108,6 +112,10 @@ hipError_t launch_pass3(const PassArgs& args, int prec, int mode, int mt, size_t
 // resident workgroups per CU, launch, counter reset.
 // `narrow`: one pencil tile per wavefront instead of the register-budget default.
 int batch_chunk(int prec, int mode, int mt, int narrow);
+// The pipelined body of a batch pass (FP64/FP32/BF16/FP16, kV2Waves
+// wavefronts): row tiles it runs with, pencils per tile and LDS bytes, or
+// false if the class has none or n exceeds the batch limit.
+bool batch_plan3(int prec, int mode, int mt, int* body_mt, int* chunk, size_t* smem);
 int batch_mt(int prec, int mt);
 size_t batch_lds_bytes(int prec, int n, bool fused);
 hipError_t batch_resident(int prec, size_t smem, int* per_cu);

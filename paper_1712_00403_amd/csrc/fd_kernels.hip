@@ -136,6 +136,25 @@ int batch_chunk(int prec, int mode, int mt, int narrow) {
   }
 }
 
+template <int P> static void batch_plan3_p(int mode, int mt, int* chunk, size_t* smem) {
+  *chunk = v3_np<P>(mt, mode, kV2Waves);
+  *smem = v3_lds_bytes<P>(mt, mode, kV2Waves);
+}
+
+bool batch_plan3(int prec, int mode, int mt, int* body_mt, int* chunk, size_t* smem) {
+  if (prec > 3 || mode < 0 || mode > 2) return false;
+  const int m = v3_mt(prec, mt);
+  if (m < 1 || m > kBatchMaxMT) return false;
+  switch (prec) {
+    case 0: batch_plan3_p<0>(mode, m, chunk, smem); break;
+    case 1: batch_plan3_p<1>(mode, m, chunk, smem); break;
+    case 2: batch_plan3_p<2>(mode, m, chunk, smem); break;
+    default: batch_plan3_p<3>(mode, m, chunk, smem); break;
+  }
+  *body_mt = m;
+  return *smem <= 160 * 1024;
+}
+
 int batch_mt(int prec, int mt) {
   (void)prec;
   return (mt + 1) / 2 * 2;

@@ -310,8 +310,19 @@ class Batch:
     def apply(self, stream=None):
         _check(lib().fd_batch_apply(self.handle, _stream_handle(stream)))
 
+    WIDE, NARROW, PIPELINED = 0, 1, 2  # body choices of a stage
+
+    @staticmethod
+    def config_of(choices):
+        """Configuration word of per-stage body choices (stage s in bits 2s, 2s + 1)."""
+        return sum(int(c) << (2 * s) for s, c in enumerate(choices))
+
+    @staticmethod
+    def choices_of(config):
+        return [(int(config) >> (2 * s)) & 3 for s in range(5)]
+
     def tune(self, stream=None, reps=3):
-        """Choose the tile width of every stage by timing (greedy); returns the bit mask of narrow stages."""
+        """Choose the body of every stage by timing (greedy); returns the configuration word."""
         c = ctypes.c_int32(0)
         _check(lib().fd_batch_tune(self.handle, _stream_handle(stream), int(reps), ctypes.byref(c)))
         return c.value

@@ -69,8 +69,15 @@ def _build(prec):
     return pcs, _oracle_refs()
 
 
+ALL_NARROW = 0b0101010101
+ALL_PIPELINED = 0b1010101010
+MIXED = 0b0110011000  # stages 0..4: wide, pipelined, narrow, pipelined, narrow
+
+
 @pytest.mark.parametrize("prec,config", [("f64", 0), ("f32", 0), ("bf16", 0), ("f16", 0), ("bf16_split", 0),
-                                         ("f32", 31), ("bf16", 31), ("f64", 10)])
+                                         ("f32", ALL_NARROW), ("bf16", ALL_NARROW), ("f64", MIXED),
+                                         ("f64", ALL_PIPELINED), ("f32", ALL_PIPELINED), ("bf16", ALL_PIPELINED),
+                                         ("f16", ALL_PIPELINED), ("bf16_split", ALL_PIPELINED), ("f32", MIXED)])
 def test_persistent_batch_matches_oracle(prec, config):
     _case(f"persistent batch of {len(PATCHES)} heterogeneous patches, prec={prec}, config={config}")
     from paper_1712_00403_amd import fd
@@ -87,7 +94,7 @@ def test_persistent_batch_matches_oracle(prec, config):
         works += pc.works(rt.data_ptr(), zt.data_ptr(), nrhs)
     batch = fd.Batch(works)
     if config:
-        batch.set_config(config)  # bit s: stage s with one pencil tile per wavefront
+        batch.set_config(config)  # stage s: bits 2s, 2s + 1 (0 wide, 1 narrow, 2 pipelined)
     info = batch.info()
     print(f"  tiles {info['tiles']}, grid {info['grid']}, config {info['config']}", flush=True)
     outs = []
@@ -126,7 +133,7 @@ def test_persistent_batch_tuning_keeps_results():
     batch = fd.Batch(works)
     choice = batch.tune(reps=2)
     assert batch.info()["config"] == choice
-    assert 0 <= choice < 32
+    assert 0 <= choice < 1024 and all(c < 3 for c in fd.Batch.choices_of(choice))
     batch.apply()
     batch.check()
     torch.cuda.synchronize()
@@ -148,4 +155,13 @@ def test_persistent_batch_rejects_large_factors():
     r = torch.zeros((1, pc.N), dtype=torch.float32, device="cuda")
     with pytest.raises(fd.FDError):
         fd.Batch(pc.works(r.data_ptr(), r.data_ptr(), 1))
+    pc.close()
+    pc = BlockPreconditioner(workloads.taylor_hood_problem((4, 4, 4), 2), precision="f32")
+    r = torch.zeros((1, pc.N), dtype=torch.float32, device="cuda")
+    z = torch.zeros_like(r)
+    batch = fd.Batch(pc.works(r.data_ptr(), z.data_ptr(), 1))
+    for bad in (-1, 3, 1 << 10):  # a choice of 3, words out of range
+        with pytest.raises(fd.FDError):
+            batch.set_config(bad)
+    batch.close()
     pc.close()
