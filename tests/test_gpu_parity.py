@@ -53,8 +53,11 @@ def _run_plan(plan, r, inplace=False, ld=None):
     return res[:, :N].astype(np.float64)
 
 
+# orders 16 (MT - 1) + 1 (17, 33, 65: one row in the last row tile) in every
+# direction, i.e. in each of the three pass kinds
 CASES_3D = [((3, 4, 5), 2, (2.0, 1.0, 1.0)), ((18, 10, 22), 3, (1.0, 2.0, 1.0)),
-            ((8, 33, 5), 1, (1.0, 1.0, 2.0)), ((6, 7, 9), 5, (1.0, 1.0, 1.0))]
+            ((8, 33, 5), 1, (1.0, 1.0, 2.0)), ((6, 7, 9), 5, (1.0, 1.0, 1.0)),
+            ((8, 16, 32), 3, (1.0, 1.0, 1.0)), ((32, 8, 16), 3, (1.0, 3.0, 1.0))]
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "bf16_split", "f16", "f16_split"])
@@ -73,7 +76,7 @@ def test_fd3d_velocity_block(prec, n_el, p, w):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "bf16_split", "f16", "f16_split"])
-@pytest.mark.parametrize("n_el,p", [((16, 16), 2), ((13, 29), 3), ((2, 3), 1), ((60, 40), 4)])
+@pytest.mark.parametrize("n_el,p", [((16, 16), 2), ((13, 29), 3), ((2, 3), 1), ((60, 40), 4), ((16, 32), 3)])
 def test_fd2d_velocity_block(prec, n_el, p):
     _case(f"fd2d velocity n_el={n_el} p={p} prec={prec}")
     Ks, Ms = _vel_factors(n_el, p)
