@@ -194,6 +194,12 @@ fd_status fd_destroy(fd_plan plan);
 /* Plan queries: N = prod(n); device bytes held by the plan. */
 int64_t fd_plan_size(fd_plan plan);
 size_t fd_plan_device_bytes(fd_plan plan);
+/* Device workspace an apply of `nrhs` vectors needs beyond the plan and the
+ * caller's r and z: 0. The first pass reads r and writes z, every later pass
+ * of Algorithm 1 runs in place on z (a tile reads all of its pencils before
+ * it stores them, and tiles own disjoint pencils), so callers that budget
+ * device memory count only the plan bytes and their vectors. */
+size_t fd_workspace_bytes(fd_plan plan, int32_t nrhs);
 
 /* Copy the FP64 factors of direction `dir` back to host arrays (U: n*n
  * column-major, d: n; either may be NULL). For tests and diagnostics. */

@@ -800,6 +800,12 @@ int64_t fd_plan_size(fd_plan plan) { return plan ? plan->N : 0; }
 
 size_t fd_plan_device_bytes(fd_plan plan) { return plan ? plan->dev_bytes : 0; }
 
+size_t fd_workspace_bytes(fd_plan plan, int32_t nrhs) {
+  (void)plan;
+  (void)nrhs;
+  return 0;
+}
+
 fd_status fd_plan_factors(fd_plan plan, int32_t dir, double* U, double* d) {
   if (!plan || dir < 0 || dir >= plan->ndim) return fail(FD_E_ARG, "fd_plan_factors: bad plan or direction");
   const int m = plan->n[dir];

@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "FD_OK", 1: "FD_E_ARG", 2: "FD_E_NOTSPD", 3: "FD_E_NOMEM", 4:
 # every symbol declared in include/fd.h
 EXPORTS = ("fd_assemble_1d", "fd_quadrature_1d", "fd_factor_1d", "fd_geometry_coefficients",
            "fd_separable_factors", "fd_operator_diagonal", "fd_setup", "fd_destroy",
-           "fd_plan_size", "fd_plan_device_bytes", "fd_plan_factors", "fd_apply",
+           "fd_plan_size", "fd_plan_device_bytes", "fd_workspace_bytes", "fd_plan_factors", "fd_apply",
            "fd_apply_batched", "fd_batch_create", "fd_batch_apply", "fd_batch_tune", "fd_batch_set_config",
            "fd_batch_info", "fd_batch_check", "fd_batch_destroy", "fd_timing_enable", "fd_timing_read", "fd_timing_launches", "fd_last_error")
 
@@ -72,6 +72,8 @@ def lib():
     L.fd_plan_size.restype = ctypes.c_int64
     L.fd_plan_device_bytes.argtypes = [ctypes.c_void_p]
     L.fd_plan_device_bytes.restype = ctypes.c_size_t
+    L.fd_workspace_bytes.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    L.fd_workspace_bytes.restype = ctypes.c_size_t
     L.fd_plan_factors.argtypes = [ctypes.c_void_p, ctypes.c_int32, c_dp, c_dp]
     L.fd_apply.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                            ctypes.c_int64, ctypes.c_void_p]
@@ -231,6 +233,10 @@ class Plan:
         self.handle = h.value
         self.N = int(L.fd_plan_size(self.handle))
         self.device_bytes = int(L.fd_plan_device_bytes(self.handle))
+
+    def workspace_bytes(self, nrhs=1):
+        """Device bytes an apply of nrhs vectors needs beyond the plan, r and z."""
+        return int(lib().fd_workspace_bytes(self.handle, int(nrhs)))
 
     def factors(self, direction):
         n = self.n[direction]

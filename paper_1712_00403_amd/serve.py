@@ -239,7 +239,8 @@ class GpuExecutor:
         return pc, nbytes
 
     def io_bytes(self, pc):
-        return pc.N * (8 if pc.io_dtype == "float64" else 4)
+        # the request's result vector plus what the library reports it needs per apply
+        return pc.N * (8 if pc.io_dtype == "float64" else 4) + sum(p.workspace_bytes(1) for p in pc.plans)
 
     def launch(self, items):
         torch = self.torch

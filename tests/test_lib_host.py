@@ -34,6 +34,13 @@ def test_exports_match_header(fd):
         assert hasattr(L, name), name
 
 
+def test_workspace_query_is_zero(fd):
+    # every pass after the first runs in place on z: no device workspace per apply
+    L = fd.lib()
+    for nrhs in (1, 16, 1024):
+        assert L.fd_workspace_bytes(None, nrhs) == 0
+
+
 @pytest.mark.parametrize("n_el,deg,reg,bc", [(16, 3, 1, True), (64, 4, 2, True), (67, 3, 2, False),
                                              (5, 1, 0, True), (9, 6, 4, False), (3, 2, -1, False)])
 def test_assembly_matches_oracle(fd, n_el, deg, reg, bc):
