@@ -236,6 +236,10 @@ void v3_factor(int n, const double* F, int prec, bool second, void* dst) {
         const int w = c & 31, hi = w >> 4, g = (w & 15) >> 2, j = w & 3;
         pos = (c & ~31) | (8 * g + 4 * hi + j);
       }
+      // FP64/FP32: rows with bit 3 set swap the halves of each 16-byte chunk
+      // (the LDS bank layout of the pipelined kernels, rhalf)
+      if (prec == 0) pos ^= rhalf(r);
+      if (prec == 1) pos ^= 2 * rhalf(r);
       const double v = F[r + size_t(n) * c];
       const size_t idx = size_t(r) * ld + pos;
       if (prec == 0) reinterpret_cast<double*>(dst)[idx] = v;
