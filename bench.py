@@ -28,7 +28,7 @@ METRIC = "FD applies/s & DOF/s, 3D p=3 64^3 elem; mixed vs FP64 at rel-err; p50/
 KERNEL_SOURCES = ["fd_pass3.inc", "fd_pass2.inc", "fd_pass.inc", "fd_internal.h", "fd_pass_f64.hip", "fd_pass_f32.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fd_pass3_fused_64cube_p3_traffic.json")
 PEAKS = {"f64": 78.6e12, "f32": 157.3e12, "bf16": 2.5e15, "bf16_split": 2.5e15, "f16": 2.5e15,
-         "f16_split": 2.5e15}
+         "f16_split": 2.5e15, "fp8_split": 5.0e15}
 HBM_PEAK = 8.0e12
 
 
@@ -79,7 +79,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--precisions", default="f64,f32,bf16,f16,bf16_split,f16_split")
+    ap.add_argument("--precisions", default="f64,f32,bf16,f16,bf16_split,f16_split,fp8_split")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--only", default=None, help="time only this precision (profiling runs)")
     ap.add_argument("--batch", default="bf16,f32",

@@ -55,14 +55,20 @@ typedef enum {
  * the Lambda^{-1} values are FP64 for every precision.
  *  FD_BF16 / FD_F16: operands rounded to bf16 / fp16, FP32 MFMA accumulation.
  *  FD_BF16_SPLIT / FD_F16_SPLIT: both operands split as hi + lo in the
- *  16-bit type; the products hi*hi + hi*lo + lo*hi are accumulated in FP32. */
+ *  16-bit type; the products hi*hi + hi*lo + lo*hi are accumulated in FP32.
+ *  FD_FP8_SPLIT: the same split with FP8 E4M3 operands (FP32 accumulation);
+ *  each pass scales its data and each factor image by powers of two so that
+ *  the 448 range limit is not reached (undone exactly on output). Only for
+ *  plans without diag_target and with every n[i] <= 224, and not in
+ *  persistent batches (FD_E_UNSUPPORTED otherwise). */
 typedef enum {
   FD_F64 = 0,
   FD_F32 = 1,
   FD_BF16 = 2,
   FD_F16 = 3,
   FD_BF16_SPLIT = 4,
-  FD_F16_SPLIT = 5
+  FD_F16_SPLIT = 5,
+  FD_FP8_SPLIT = 6
 } fd_precision;
 
 typedef struct fd_plan_s* fd_plan;

@@ -35,7 +35,8 @@ struct fd_plan_s {
   const void* v_snd[3] = {nullptr, nullptr, nullptr};  // padded U_i as second product of the fused pass
   const double* d_dev[3] = {nullptr, nullptr, nullptr};
   double lam_w[3] = {1, 1, 1};                          // weights used for Lambda on device
-  float xs[5] = {1, 1, 1, 1, 1}, qs = 1.0f;             // FP16 range scaling per stage
+  float xs[5] = {1, 1, 1, 1, 1}, qs = 1.0f;             // FP16 / FP8 range scaling per stage
+  float fs[3] = {1, 1, 1};                              // FP8: scale of the factor images per direction
   const void* scale_dev = nullptr;                      // D^{-1/2}, I/O type
   int MT[3] = {0, 0, 0}, KS[3] = {0, 0, 0};
   int device = 0;
@@ -148,7 +149,8 @@ bool unit_pass(const fd_plan_s* p, const fd_work& wk, int stage, fdk::PassDesc& 
   }
   u.xscale = p->xs[stage];
   u.qscale = fused ? p->qs : 1.0f;
-  u.oscale = 1.0f / (u.xscale * u.qscale);
+  // (FP8: the factor images carry fs per product)
+  u.oscale = 1.0f / (u.xscale * u.qscale * p->fs[dir] * (fused ? p->fs[dir] : 1.0f));
   u.MT = p->MT[dir];
   u.KS = p->KS[dir];
   u.lam_ndim = p->ndim;
@@ -209,7 +211,7 @@ fd_status run_work(int count, const fd_work* work, hipStream_t stream) {
         if (e != hipSuccess) return hip_fail(e, "timing event");
       }
     }
-    for (int prec = 0; prec <= 5; ++prec) {
+    for (int prec = 0; prec <= 6; ++prec) {
       // units of this stage and precision class
       std::vector<fdk::PassDesc> units;
       int mode = -1;
@@ -567,7 +569,15 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
   *out = nullptr;
   if (ndim != 2 && ndim != 3) return fail(FD_E_ARG, "fd_setup: ndim must be 2 or 3");
   if (!n || !M) return fail(FD_E_ARG, "fd_setup: NULL n or M");
-  if (int(prec) < 0 || int(prec) > 5) return fail(FD_E_ARG, "fd_setup: unknown precision");
+  if (int(prec) < 0 || int(prec) > 6) return fail(FD_E_ARG, "fd_setup: unknown precision");
+  if (prec == FD_FP8_SPLIT) {
+    // only the pipelined kernels have an FP8 body: no input/output scaling,
+    // every order within their row tiles
+    if (diag_target) return fail(FD_E_UNSUPPORTED, "fd_setup: FD_FP8_SPLIT plans take no diag_target");
+    for (int i = 0; i < ndim && n; ++i)
+      if (n[i] > 16 * fdk::v2_max_mt_of(FD_FP8_SPLIT))
+        return fail(FD_E_UNSUPPORTED, "fd_setup: FD_FP8_SPLIT needs every n[i] <= 224");
+  }
   auto p = new (std::nothrow) fd_plan_s();
   if (!p) return fail(FD_E_NOMEM, "fd_setup: host allocation");
   p->ndim = ndim;
@@ -663,7 +673,18 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
   // model assumes residual entries of RMS 1 (times D^{-1/2} when scaled): a
   // product by U_i multiplies the RMS by ||U_i||_F / sqrt(n_i), the division
   // by Lambda by the RMS of 1 / Lambda (estimated on 4096 fixed multi-indices).
-  if (p->prec == FD_F16 || p->prec == FD_F16_SPLIT) {
+  // FP8 (largest finite 448): the same model with the RMS of every converted
+  // tensor placed at 4, and each factor image scaled by the power of two that
+  // puts its largest entry in [112, 224); the output scale undoes both.
+  const bool fp8 = p->prec == FD_FP8_SPLIT;
+  if (fp8) {
+    for (int i = 0; i < ndim; ++i) {
+      double mx = 0.0;
+      for (double v : p->U[i]) mx = std::max(mx, std::fabs(v));
+      p->fs[i] = mx > 0 ? float(std::ldexp(1.0, int(std::floor(std::log2(224.0 / mx))))) : 1.0f;
+    }
+  }
+  if (p->prec == FD_F16 || p->prec == FD_F16_SPLIT || fp8) {
     double gain[3] = {1, 1, 1};
     for (int i = 0; i < ndim; ++i) {
       double f = 0.0;
@@ -690,7 +711,10 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
       }
       inv_lam = std::sqrt(acc2 / 4096.0);
     }
-    auto pow2 = [](double rms) { return float(std::ldexp(1.0, -int(std::lround(std::log2(rms))))); };
+    const double target = fp8 ? 4.0 : 1.0;
+    auto pow2 = [target](double rms) {
+      return float(std::ldexp(1.0, -int(std::lround(std::log2(rms / target)))));
+    };
     const int last = ndim - 1;
     double in = r0;
     for (int i = 0; i < last; ++i) {  // forward passes before the fused one
@@ -699,7 +723,7 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
     }
     const int fused_stage = 2;  // 3D: stages 0, 1 then 2; 2D: stage 0 then 2
     p->xs[fused_stage] = pow2(in);
-    p->qs = pow2(in * p->xs[fused_stage] * gain[last] * inv_lam);
+    p->qs = pow2(in * p->xs[fused_stage] * p->fs[last] * gain[last] * inv_lam);
     double q = in * gain[last] * inv_lam;  // unscaled RMS after the division
     double back = q * gain[last];
     if (ndim == 3) {
@@ -730,11 +754,22 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
   if (diag_target) { offs = total; total = align(total + eb * size_t(p->N)); }
   std::vector<unsigned char> host(total, 0);
   std::vector<double> Ft;
+  std::vector<float> stage8[3];
   for (int i = 0; i < ndim; ++i) {
     const int m = n[i];
     Ft.assign(size_t(m) * m, 0.0);
     for (int r = 0; r < m; ++r)
       for (int c = 0; c < m; ++c) Ft[r + size_t(m) * c] = p->U[i][c + size_t(m) * r];
+    if (fp8) {
+      // FP32 images (scaled), converted to FP8 hi/lo on the device below
+      const size_t e = size_t(fdk::v3_ld(m, p->prec)) * fdk::v3_ld(m, p->prec);
+      stage8[i].assign(3 * e, 0.0f);
+      fdk::v3_factor_f32(m, Ft.data(), false, p->fs[i], stage8[i].data());
+      fdk::v3_factor_f32(m, p->U[i].data(), false, p->fs[i], stage8[i].data() + e);
+      fdk::v3_factor_f32(m, p->U[i].data(), true, p->fs[i], stage8[i].data() + 2 * e);
+      std::memcpy(host.data() + offd[i], dl[i].data(), sizeof(double) * m);
+      continue;
+    }
     fdk::pack_factor(m, Ft.data(), p->prec, host.data() + off[i][0]);
     fdk::pack_factor(m, p->U[i].data(), p->prec, host.data() + off[i][1]);
     fdk::plain_factor(m, Ft.data(), p->prec, host.data() + offp[i][0]);
@@ -766,6 +801,25 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
   }
   p->dev_bytes = total;
   unsigned char* base = static_cast<unsigned char*>(p->dev);
+  if (fp8) {
+    size_t sb = 0;
+    for (int i = 0; i < ndim; ++i) sb = std::max(sb, stage8[i].size() * sizeof(float));
+    void* tmp = nullptr;
+    e = hipMalloc(&tmp, sb);
+    for (int i = 0; i < ndim && e == hipSuccess; ++i) {
+      const int64_t ent = int64_t(fdk::v3_ld(n[i], p->prec)) * fdk::v3_ld(n[i], p->prec);
+      e = hipMemcpy(tmp, stage8[i].data(), stage8[i].size() * sizeof(float), hipMemcpyHostToDevice);
+      for (int j = 0; j < 3 && e == hipSuccess; ++j)
+        e = fdk::fp8s_image(static_cast<const float*>(tmp) + j * ent, base + offv[i][j], ent, nullptr);
+      if (e == hipSuccess) e = hipDeviceSynchronize();
+    }
+    if (tmp) (void)hipFree(tmp);
+    if (e != hipSuccess) {
+      (void)hipFree(p->dev);
+      delete p;
+      return e == hipErrorOutOfMemory ? fail(FD_E_NOMEM, "fd_setup: device allocation") : hip_fail(e, "FP8 images");
+    }
+  }
   for (int i = 0; i < ndim; ++i) {
     p->f_fwd[i] = base + off[i][0];
     p->f_bwd[i] = base + off[i][1];
@@ -835,6 +889,8 @@ fd_status fd_batch_create(int32_t count, const fd_work* work, fd_batch* out) {
         return fail(FD_E_UNSUPPORTED, "fd_batch_create: factor order above 128 (use fd_apply_batched)");
     if (work[i].plan->prec != work[0].plan->prec)
       return fail(FD_E_UNSUPPORTED, "fd_batch_create: plans of different precision classes");
+  if (count > 0 && work[0].plan->prec == FD_FP8_SPLIT)
+    return fail(FD_E_UNSUPPORTED, "fd_batch_create: no persistent-batch body for FD_FP8_SPLIT");
   }
   auto* b = new fd_batch_s;
   b->prec = work[0].plan->prec;

@@ -106,6 +106,13 @@ hipError_t launch_pass2(const PassArgs& args, int prec, int mode, int bucket, si
 // Pipelined kernels (FP64/FP32, factor and pencil blocks streamed into LDS
 // stages by direct global->LDS loads). mt is the exact row-tile count.
 bool v3_plan(int prec, int mode, int max_n, int mt, int* chunk, size_t* smem);
+// Largest row-tile count of the pipelined kernels of a class.
+int v2_max_mt_of(int prec);
+// FP8 split class: the FP32 image of a pipelined factor scaled by `scale`
+// (ld x ld floats, ld = v3_ld(n, 6)), and its device conversion to the FP8
+// hi/lo image (`entries` a multiple of 8; asynchronous on `stream`).
+void v3_factor_f32(int n, const double* F, bool second, float scale, float* dst);
+hipError_t fp8s_image(const float* src, void* dst, int64_t entries, hipStream_t stream);
 hipError_t launch_pass3(const PassArgs& args, int prec, int mode, int mt, size_t smem, hipStream_t stream);
 // Bytes of one plain factor (n x n in the storage type, hi and lo planes for split).
 // Batched persistent launch: pencils per tile and LDS bytes of a pass body,

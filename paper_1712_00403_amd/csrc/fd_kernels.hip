@@ -47,6 +47,9 @@ extern template hipError_t launch3_p<0>(const PassArgs&, int, int, size_t, hipSt
 extern template hipError_t launch3_p<1>(const PassArgs&, int, int, size_t, hipStream_t);
 extern template hipError_t launch3_p<2>(const PassArgs&, int, int, size_t, hipStream_t);
 extern template hipError_t launch3_p<3>(const PassArgs&, int, int, size_t, hipStream_t);
+extern template hipError_t launch3_p<6>(const PassArgs&, int, int, size_t, hipStream_t);
+
+int v2_max_mt_of(int prec) { return prec == 0 ? v2_max_mt<0>() : prec == 1 ? v2_max_mt<1>() : v2_max_mt<2>(); }
 
 template <int P>
 static bool v3_plan_p(int mode, int max_n, int mt, int* chunk, size_t* smem) {
@@ -66,6 +69,7 @@ bool v3_plan(int prec, int mode, int max_n, int mt, int* chunk, size_t* smem) {
   if (prec == 1) return v3_plan_p<1>(mode, max_n, mt, chunk, smem);
   if (prec == 2) return v3_plan_p<2>(mode, max_n, v3_mt(prec, mt), chunk, smem);
   if (prec == 3) return v3_plan_p<3>(mode, max_n, v3_mt(prec, mt), chunk, smem);
+  if (prec == 6) return v3_plan_p<6>(mode, max_n, v3_mt(prec, mt), chunk, smem);
   return false;
 }
 
@@ -75,6 +79,7 @@ hipError_t launch_pass3(const PassArgs& args, int prec, int mode, int mt, size_t
   if (prec == 1) return launch3_p<1>(args, mode, mt, smem, stream);
   if (prec == 2) return launch3_p<2>(args, mode, v3_mt(prec, mt), smem, stream);
   if (prec == 3) return launch3_p<3>(args, mode, v3_mt(prec, mt), smem, stream);
+  if (prec == 6) return launch3_p<6>(args, mode, v3_mt(prec, mt), smem, stream);
   return hipErrorInvalidValue;
 }
 
@@ -206,6 +211,7 @@ hipError_t batch_reset(uint32_t* barrier, int32_t* error, hipStream_t stream) {
 }
 
 size_t plain_bytes(int n, int prec) {
+  if (prec == 6) return 0;  // the FP8 class has pipelined images only
   const size_t per = size_t(n) * n * elem_bytes(prec);
   return (prec == 4 || prec == 5) ? 2 * per : per;
 }
@@ -217,7 +223,7 @@ int v3_ld(int n, int prec) {
 }
 
 size_t v3_factor_bytes(int n, int prec) {
-  if (prec < 0 || prec > 3) return 0;
+  if (prec < 0 || (prec > 3 && prec != 6)) return 0;
   const size_t eb = prec == 0 ? 8 : (prec == 1 ? 4 : 2);
   return size_t(v3_ld(n, prec)) * v3_ld(n, prec) * eb;
 }
@@ -249,6 +255,20 @@ void v3_factor(int n, const double* F, int prec, bool second, void* dst) {
     }
 }
 
+void v3_factor_f32(int n, const double* F, bool second, float scale, float* dst) {
+  const int ld = v3_ld(n, 6);
+  std::memset(dst, 0, sizeof(float) * size_t(ld) * ld);
+  for (int r = 0; r < n; ++r)
+    for (int c = 0; c < n; ++c) {
+      int pos = c;
+      if (second) {  // as the 16-bit classes: column 4 g + j at 8 g + j, 16 + 4 g + j at 8 g + 4 + j
+        const int w = c & 31, hi = w >> 4, g = (w & 15) >> 2, j = w & 3;
+        pos = (c & ~31) | (8 * g + 4 * hi + j);
+      }
+      dst[size_t(r) * ld + pos] = float(F[r + size_t(n) * c] * double(scale));
+    }
+}
+
 void plain_factor(int n, const double* F, int prec, void* dst) {
   const size_t nn = size_t(n) * n;
   for (int r = 0; r < n; ++r)
@@ -276,6 +296,7 @@ int mfma_kstep(int prec) { return (prec <= 1) ? 4 : 32; }
 static size_t elem_bytes(int prec) { return prec == 0 ? 8 : prec == 1 ? 4 : 2; }
 
 size_t packed_bytes(int n, int prec) {
+  if (prec == 6) return 0;
   const int ks = mfma_kstep(prec);
   const size_t MT = (n + 15) / 16, KS = (n + ks - 1) / ks;
   const size_t per = MT * KS * 16 * ks * elem_bytes(prec);

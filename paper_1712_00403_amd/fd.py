@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfd.so")
 
 FD_OK, FD_E_ARG, FD_E_NOTSPD, FD_E_NOMEM, FD_E_HIP, FD_E_UNSUPPORTED = range(6)
-PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "bf16_split": 4, "f16_split": 5}
+PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "bf16_split": 4, "f16_split": 5, "fp8_split": 6}
 STATUS_NAMES = {0: "FD_OK", 1: "FD_E_ARG", 2: "FD_E_NOTSPD", 3: "FD_E_NOMEM", 4: "FD_E_HIP",
                 5: "FD_E_UNSUPPORTED"}
 

@@ -16,7 +16,9 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 # per-precision tolerance on ||z - z_oracle|| / ||z_oracle||
-TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-2, "bf16_split": 1e-4, "f16": 5e-3, "f16_split": 1e-4}
+# (FP8 split: a rounding emulation of the mode products puts it at 2.5-3e-3)
+TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-2, "bf16_split": 1e-4, "f16": 5e-3, "f16_split": 1e-4,
+       "fp8_split": 1e-2}
 
 
 def _fd():
@@ -60,7 +62,7 @@ CASES_3D = [((3, 4, 5), 2, (2.0, 1.0, 1.0)), ((18, 10, 22), 3, (1.0, 2.0, 1.0)),
             ((8, 16, 32), 3, (1.0, 1.0, 1.0)), ((32, 8, 16), 3, (1.0, 3.0, 1.0))]
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "bf16_split", "f16", "f16_split"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "bf16_split", "f16", "f16_split", "fp8_split"])
 @pytest.mark.parametrize("n_el,p,w", CASES_3D)
 def test_fd3d_velocity_block(prec, n_el, p, w):
     _case(f"fd3d velocity n_el={n_el} p={p} w={w} prec={prec}")
@@ -75,7 +77,7 @@ def test_fd3d_velocity_block(prec, n_el, p, w):
     plan.close()
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "bf16_split", "f16", "f16_split"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "bf16_split", "f16", "f16_split", "fp8_split"])
 @pytest.mark.parametrize("n_el,p", [((16, 16), 2), ((13, 29), 3), ((2, 3), 1), ((60, 40), 4), ((16, 32), 3)])
 def test_fd2d_velocity_block(prec, n_el, p):
     _case(f"fd2d velocity n_el={n_el} p={p} prec={prec}")
@@ -90,7 +92,7 @@ def test_fd2d_velocity_block(prec, n_el, p):
     plan.close()
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f16", "fp8_split"])
 @pytest.mark.parametrize("n_el,p", [((5, 9, 4), 2), ((20, 11, 17), 3), ((7, 12), 2)])
 def test_pressure_mass_block(prec, n_el, p):
     _case(f"pressure mass n_el={n_el} p={p} prec={prec}")
@@ -175,7 +177,7 @@ def test_block_preconditioner_mixed_batch(prec):
         pc.close()
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "fp8_split"])
 def test_full_size_64cube_p3(prec):
     """The 64^3, p = 3 block (n_V = 129, n_Q = 67) in the launch configuration of the bench."""
     _case(f"full-size 64^3 p=3 block, prec={prec}")
@@ -300,3 +302,20 @@ def test_plan_rejects_order_above_256():
     with pytest.raises(fd.FDError) as e:
         fd.Plan(Ks, Ms)
     assert e.value.status == fd.FD_E_ARG
+
+
+def test_fp8_split_limits():
+    _case("FP8 split plan limits: no diag_target, n <= 224, no persistent batch")
+    fd = _fd()
+    Ks, Ms = _vel_factors((4, 5, 6), 2)
+    with pytest.raises(fd.FDError, match="FD_E_UNSUPPORTED"):
+        fd.Plan(Ks, Ms, precision="fp8_split", diag_target=np.ones(int(np.prod([k.shape[0] for k in Ks]))))
+    Kb, Mb = _vel_factors((120, 3, 3), 2)  # n = 240 in direction 1
+    with pytest.raises(fd.FDError, match="FD_E_UNSUPPORTED"):
+        fd.Plan(Kb, Mb, precision="fp8_split")
+    plan = fd.Plan(Ks, Ms, precision="fp8_split")
+    r = torch.zeros((1, plan.N), dtype=torch.float32, device="cuda")
+    z = torch.zeros_like(r)
+    with pytest.raises(fd.FDError, match="FD_E_UNSUPPORTED"):
+        fd.Batch([(plan, r.data_ptr(), z.data_ptr(), 1, plan.N)])
+    plan.close()
