@@ -53,7 +53,7 @@ int v2_max_mt_of(int prec) { return prec == 0 ? v2_max_mt<0>() : prec == 1 ? v2_
 
 template <int P>
 static bool v3_plan_p(int mode, int max_n, int mt, int* chunk, size_t* smem) {
-  if (mt < 1 || mt > v2_max_mt<P>()) return false;
+  if (mt < 1 || mt > v3_max_mt<P>(mode)) return false;
   (void)max_n;
   const size_t bytes = v3_lds_bytes<P>(mt, mode);
   if (bytes > 160 * 1024) return false;
