@@ -213,97 +213,124 @@ fd_status run_work(int count, const fd_work* work, hipStream_t stream) {
     }
     for (int prec = 0; prec <= 6; ++prec) {
       // units of this stage and precision class
-      std::vector<fdk::PassDesc> units;
+      std::vector<fdk::PassDesc> units, split_fwd, split_bwd;
       int mode = -1;
       for (int i = 0; i < count; ++i) {
         const fd_work& wk = work[i];
         if (wk.nrhs == 0 || wk.plan->prec != prec) continue;
         fdk::PassDesc u;
         if (!unit_pass(wk.plan, wk, stage, u)) continue;
-        units.push_back(u);
         mode = stage_mode(u);
+        // FP64 last-mode passes beyond the fused pipelined kernel (n > 144)
+        // but within the single-pass one run as two pipelined passes: the
+        // forward product with Lambda^{-1} applied before its store (mode 3),
+        // then the backward product in place (mode 1)
+        int c3 = 0;
+        size_t s3 = 0;
+        if (kernel_family >= 3 && prec == FD_F64 && mode == 2 && !fdk::v3_plan(prec, 2, u.n, u.MT, &c3, &s3) &&
+            fdk::v3_plan(prec, 3, u.n, u.MT, &c3, &s3) && fdk::v3_plan(prec, 1, u.n, u.MT, &c3, &s3)) {
+          split_fwd.push_back(u);
+          fdk::PassDesc v = u;
+          v.in = u.out;
+          v.flags &= ~fdk::kFuseLambda;
+          v.pv1 = wk.plan->v_bwd[wk.plan->ndim - 1];
+          split_bwd.push_back(v);
+          continue;
+        }
+        units.push_back(u);
       }
-      if (units.empty()) continue;
-      // Kernel families: 3 = pipelined LDS GEMM (FP64/FP32), 2 = factor resident
-      // in LDS, 1 = factor fragments from global memory. Family 3 launches
-      // group units of one factor order n, family 2 units of one row-tile
-      // count; family 1 takes the rest in one launch.
-      std::vector<int> group(units.size(), -1);  // family * 1000 + n or row tiles
-      for (size_t k = 0; k < units.size(); ++k) {
-        int b = 0, c = 0;
-        size_t sm = 0;
-        const bool pre = (units[k].flags & fdk::kPreScale) != 0;
-        // the pipelined family (FP64/FP32) loads raw input straight into LDS
-        // and stores raw accumulators, so passes that scale their input or
-        // output run on family 2
-        const bool post = (units[k].flags & fdk::kPostScale) != 0;
-        if (kernel_family >= 3 && !pre && !post && fdk::v3_plan(prec, mode, units[k].n, units[k].MT, &c, &sm))
-          group[k] = 3000 + units[k].n;
-        else if (kernel_family >= 2 && fdk::v2_plan(prec, mode, units[k].n, units[k].MT, &b, &c, &sm))
-          group[k] = 2000 + b;
-        else
-          group[k] = 1000;
-      }
-      std::vector<int> keys(group.begin(), group.end());
-      std::sort(keys.begin(), keys.end());
-      keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
-      for (int key : keys) {
-        const int fam = key / 1000;
-        int max_n = 0, max_mt = 1;
-        for (size_t k = 0; k < units.size(); ++k)
-          if (group[k] == key) {
-            max_n = std::max(max_n, units[k].n);
-            max_mt = std::max(max_mt, units[k].MT);
-          }
-        int bucket = 0, chunk = fdk::kTileP;
-        size_t smem = 0;
-        bool ok = true;
-        if (fam == 3) ok = fdk::v3_plan(prec, mode, max_n, max_mt, &chunk, &smem);
-        if (fam == 2) ok = fdk::v2_plan(prec, mode, max_n, max_mt, &bucket, &chunk, &smem);
-        if (!ok) return fail(FD_E_HIP, "internal: kernel plan changed");
-        fdk::PassArgs args;
-        args.count = 0;
-        args.total_tiles = 0;
-        int launch_mt = 1;
-        auto flush = [&]() -> fd_status {
-          if (args.count == 0) return FD_OK;
-          LaunchRecord lr{stage, fam, max_n, prec, nullptr, nullptr};
-          if (g_timing) {
-            hipError_t e = hipEventCreate(&lr.start);
-            if (e == hipSuccess) e = hipEventCreate(&lr.end);
-            if (e == hipSuccess) e = hipEventRecord(lr.start, stream);
-            if (e != hipSuccess) return hip_fail(e, "timing event");
-          }
-          hipError_t e = fam == 3 ? fdk::launch_pass3(args, prec, mode, max_mt, smem, stream)
-                       : fam == 2 ? fdk::launch_pass2(args, prec, mode, bucket, smem, stream)
-                                  : fdk::launch_pass(args, prec, launch_mt, stream);
-          if (g_timing && e == hipSuccess) {
-            e = hipEventRecord(lr.end, stream);
-            if (e == hipSuccess) g_launch_records.push_back(lr);
-          }
+      auto run_units = [&](std::vector<fdk::PassDesc>& units, int mode) -> fd_status {
+        // Kernel families: 3 = pipelined LDS GEMM (FP64/FP32), 2 = factor resident
+        // in LDS, 1 = factor fragments from global memory. Family 3 launches
+        // group units of one factor order n, family 2 units of one row-tile
+        // count; family 1 takes the rest in one launch.
+        std::vector<int> group(units.size(), -1);  // family * 1000 + n or row tiles
+        for (size_t k = 0; k < units.size(); ++k) {
+          int b = 0, c = 0;
+          size_t sm = 0;
+          const bool pre = (units[k].flags & fdk::kPreScale) != 0;
+          // the pipelined family (FP64/FP32) loads raw input straight into LDS
+          // and stores raw accumulators, so passes that scale their input or
+          // output run on family 2
+          const bool post = (units[k].flags & fdk::kPostScale) != 0;
+          if (kernel_family >= 3 && !pre && !post && fdk::v3_plan(prec, mode, units[k].n, units[k].MT, &c, &sm))
+            group[k] = 3000 + units[k].n;
+          else if (kernel_family >= 2 && fdk::v2_plan(prec, mode, units[k].n, units[k].MT, &b, &c, &sm))
+            group[k] = 2000 + b;
+          else
+            group[k] = 1000;
+        }
+        std::vector<int> keys(group.begin(), group.end());
+        std::sort(keys.begin(), keys.end());
+        keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+        for (int key : keys) {
+          const int fam = key / 1000;
+          int max_n = 0, max_mt = 1;
+          for (size_t k = 0; k < units.size(); ++k)
+            if (group[k] == key) {
+              max_n = std::max(max_n, units[k].n);
+              max_mt = std::max(max_mt, units[k].MT);
+            }
+          int bucket = 0, chunk = fdk::kTileP;
+          size_t smem = 0;
+          bool ok = true;
+          if (fam == 3) ok = fdk::v3_plan(prec, mode, max_n, max_mt, &chunk, &smem);
+          if (fam == 2) ok = fdk::v2_plan(prec, mode, max_n, max_mt, &bucket, &chunk, &smem);
+          if (!ok) return fail(FD_E_HIP, "internal: kernel plan changed");
+          fdk::PassArgs args;
           args.count = 0;
           args.total_tiles = 0;
-          launch_mt = 1;
-          if (e != hipSuccess) return hip_fail(e, "kernel launch");
-          return FD_OK;
-        };
-        for (size_t k = 0; k < units.size(); ++k) {
-          if (group[k] != key) continue;
-          fdk::PassDesc u = units[k];
-          const int64_t NQ = int64_t(u.A) * u.B;
-          u.tiles_per_rhs = int32_t((NQ + chunk - 1) / chunk);
-          const int64_t tiles = int64_t(u.tiles_per_rhs) * u.nrhs;
-          if (tiles > 0x7fffffffLL) return fail(FD_E_ARG, "fd_apply: too many tiles in one call");
-          if (args.count == fdk::kMaxDesc || int64_t(args.total_tiles) + tiles > 0x7fffffffLL) {
-            fd_status s = flush();
-            if (s != FD_OK) return s;
+          int launch_mt = 1;
+          auto flush = [&]() -> fd_status {
+            if (args.count == 0) return FD_OK;
+            LaunchRecord lr{stage, fam, max_n, prec, nullptr, nullptr};
+            if (g_timing) {
+              hipError_t e = hipEventCreate(&lr.start);
+              if (e == hipSuccess) e = hipEventCreate(&lr.end);
+              if (e == hipSuccess) e = hipEventRecord(lr.start, stream);
+              if (e != hipSuccess) return hip_fail(e, "timing event");
+            }
+            hipError_t e = fam == 3 ? fdk::launch_pass3(args, prec, mode, max_mt, smem, stream)
+                         : fam == 2 ? fdk::launch_pass2(args, prec, mode, bucket, smem, stream)
+                                    : fdk::launch_pass(args, prec, launch_mt, stream);
+            if (g_timing && e == hipSuccess) {
+              e = hipEventRecord(lr.end, stream);
+              if (e == hipSuccess) g_launch_records.push_back(lr);
+            }
+            args.count = 0;
+            args.total_tiles = 0;
+            launch_mt = 1;
+            if (e != hipSuccess) return hip_fail(e, "kernel launch");
+            return FD_OK;
+          };
+          for (size_t k = 0; k < units.size(); ++k) {
+            if (group[k] != key) continue;
+            fdk::PassDesc u = units[k];
+            const int64_t NQ = int64_t(u.A) * u.B;
+            u.tiles_per_rhs = int32_t((NQ + chunk - 1) / chunk);
+            const int64_t tiles = int64_t(u.tiles_per_rhs) * u.nrhs;
+            if (tiles > 0x7fffffffLL) return fail(FD_E_ARG, "fd_apply: too many tiles in one call");
+            if (args.count == fdk::kMaxDesc || int64_t(args.total_tiles) + tiles > 0x7fffffffLL) {
+              fd_status s = flush();
+              if (s != FD_OK) return s;
+            }
+            u.tile_begin = args.total_tiles;
+            args.u[args.count++] = u;
+            args.total_tiles += int32_t(tiles);
+            launch_mt = std::max(launch_mt, u.MT);
           }
-          u.tile_begin = args.total_tiles;
-          args.u[args.count++] = u;
-          args.total_tiles += int32_t(tiles);
-          launch_mt = std::max(launch_mt, u.MT);
+          fd_status s = flush();
+          if (s != FD_OK) return s;
         }
-        fd_status s = flush();
+        return FD_OK;
+      };
+      if (!units.empty()) {
+        fd_status s = run_units(units, mode);
+        if (s != FD_OK) return s;
+      }
+      if (!split_fwd.empty()) {
+        fd_status s = run_units(split_fwd, 3);
+        if (s == FD_OK) s = run_units(split_bwd, 1);
         if (s != FD_OK) return s;
       }
     }
@@ -669,10 +696,15 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
   }
   // FP16 range (largest finite 65504): each pass converts its FP32 input to
   // FP16, so the input of every pass is scaled by a power of two that brings
-  // its expected RMS to 1, and the result is scaled back (exact). The RMS
-  // model assumes residual entries of RMS 1 (times D^{-1/2} when scaled): a
-  // product by U_i multiplies the RMS by ||U_i||_F / sqrt(n_i), the division
-  // by Lambda by the RMS of 1 / Lambda (estimated on 4096 fixed multi-indices).
+  // its expected RMS to 1, and the result is scaled back (exact). The model
+  // takes white residual entries of RMS r0 (the RMS of D^{-1/2} when scaled):
+  // a product along mode i by U_i^T or U_i keeps the entries' variances in
+  // product form, entry k scaled by c_i[k_i] = ||column k_i of U_i||^2, and
+  // the division by Lambda divides entry k by Lambda(k)^2. So the mean square
+  // after the forward products along modes 0..j is prod_{i<=j} mean(c_i), and
+  // after the division and backward products along modes in `back` it is the
+  // mean over k of prod_i c_i[k_i] prod_{i in back} c_i[k_i] / Lambda(k)^2,
+  // estimated on 4096 fixed multi-indices.
   // FP8 (largest finite 448): the same model with the RMS of every converted
   // tensor placed at 4, and each factor image scaled by the power of two that
   // puts its largest entry in [112, 224); the output scale undoes both.
@@ -685,10 +717,14 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
     }
   }
   if (p->prec == FD_F16 || p->prec == FD_F16_SPLIT || fp8) {
+    std::vector<double> cn[3];  // squared column norms of U_i
     double gain[3] = {1, 1, 1};
     for (int i = 0; i < ndim; ++i) {
+      cn[i].assign(n[i], 0.0);
+      for (int k = 0; k < n[i]; ++k)
+        for (int m = 0; m < n[i]; ++m) cn[i][k] += p->U[i][m + size_t(n[i]) * k] * p->U[i][m + size_t(n[i]) * k];
       double f = 0.0;
-      for (double v : p->U[i]) f += v * v;
+      for (double v : cn[i]) f += v;
       gain[i] = std::sqrt(f / n[i]);
     }
     double r0 = 1.0;
@@ -697,25 +733,33 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
       for (double v : scale) ss += v * v;
       r0 = std::sqrt(ss / double(p->N));
     }
-    double inv_lam = 1.0;
-    if (!p->mass_only) {
+    const int last = ndim - 1;
+    // mean squares after the division (sq[0]) and after the backward products
+    // along modes last, last-1 (sq[1], sq[2])
+    double sq[3] = {0.0, 0.0, 0.0};
+    {
       uint64_t st = 0x9E3779B97F4A7C15ull;
-      double acc2 = 0.0;
       for (int t = 0; t < 4096; ++t) {
-        double lam = 0.0;
+        double lam = 0.0, w = 1.0;
+        int k[3] = {0, 0, 0};
         for (int i = 0; i < ndim; ++i) {
           st = st * 6364136223846793005ull + 1442695040888963407ull;
-          lam += p->lam_w[i] * dl[i][(st >> 33) % uint64_t(n[i])];
+          k[i] = int((st >> 33) % uint64_t(n[i]));
+          lam += p->lam_w[i] * dl[i][k[i]];
+          w *= cn[i][k[i]];
         }
-        acc2 += 1.0 / (lam * lam);
+        if (p->mass_only) lam = 1.0;
+        const double v = w / (lam * lam);
+        sq[0] += v;
+        sq[1] += v * cn[last][k[last]];
+        if (ndim == 3) sq[2] += v * cn[last][k[last]] * cn[1][k[1]];
       }
-      inv_lam = std::sqrt(acc2 / 4096.0);
+      for (double& v : sq) v /= 4096.0;
     }
     const double target = fp8 ? 4.0 : 1.0;
     auto pow2 = [target](double rms) {
       return float(std::ldexp(1.0, -int(std::lround(std::log2(rms / target)))));
     };
-    const int last = ndim - 1;
     double in = r0;
     for (int i = 0; i < last; ++i) {  // forward passes before the fused one
       p->xs[i] = pow2(in);
@@ -723,15 +767,16 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
     }
     const int fused_stage = 2;  // 3D: stages 0, 1 then 2; 2D: stage 0 then 2
     p->xs[fused_stage] = pow2(in);
-    p->qs = pow2(in * p->xs[fused_stage] * p->fs[last] * gain[last] * inv_lam);
-    double q = in * gain[last] * inv_lam;  // unscaled RMS after the division
-    double back = q * gain[last];
+    // the fused pass converts acc / Lambda, where acc carries its input scale
+    // and the factor image scale
+    p->qs = pow2(r0 * std::sqrt(sq[0]) * p->xs[fused_stage] * p->fs[last]);
     if (ndim == 3) {
-      p->xs[3] = pow2(back);
-      back *= gain[1];
+      p->xs[3] = pow2(r0 * std::sqrt(sq[1]));
+      p->xs[4] = pow2(r0 * std::sqrt(sq[2]));
+    } else {
+      p->xs[4] = pow2(r0 * std::sqrt(sq[1]));
+      p->xs[0] = pow2(r0);
     }
-    p->xs[4] = pow2(back);
-    if (ndim == 2) p->xs[0] = pow2(r0);
   }
   // Pack U_i^T (forward) and U_i (backward) in fragment order.
   const int ks = fdk::mfma_kstep(p->prec);

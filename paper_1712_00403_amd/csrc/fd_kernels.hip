@@ -65,6 +65,7 @@ static bool v3_plan_p(int mode, int max_n, int mt, int* chunk, size_t* smem) {
 int v3_mt(int prec, int mt) { return prec >= 2 ? (mt + 1) / 2 * 2 : mt; }
 
 bool v3_plan(int prec, int mode, int max_n, int mt, int* chunk, size_t* smem) {
+  if (mode == 3 && prec != 0) return false;  // (forward + Lambda pass: FP64 only)
   if (prec == 0) return v3_plan_p<0>(mode, max_n, mt, chunk, smem);
   if (prec == 1) return v3_plan_p<1>(mode, max_n, mt, chunk, smem);
   if (prec == 2) return v3_plan_p<2>(mode, max_n, v3_mt(prec, mt), chunk, smem);

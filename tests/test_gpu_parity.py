@@ -78,7 +78,9 @@ def test_fd3d_velocity_block(prec, n_el, p, w):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "bf16_split", "f16", "f16_split", "fp8_split"])
-@pytest.mark.parametrize("n_el,p", [((16, 16), 2), ((13, 29), 3), ((2, 3), 1), ((60, 40), 4), ((16, 32), 3)])
+# ((10, 80), 3): n_2 = 161, the FP64 last mode beyond the fused pipelined kernel
+@pytest.mark.parametrize("n_el,p", [((16, 16), 2), ((13, 29), 3), ((2, 3), 1), ((60, 40), 4), ((16, 32), 3),
+                                    ((10, 80), 3)])
 def test_fd2d_velocity_block(prec, n_el, p):
     _case(f"fd2d velocity n_el={n_el} p={p} prec={prec}")
     Ks, Ms = _vel_factors(n_el, p)
