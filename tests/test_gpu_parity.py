@@ -321,3 +321,25 @@ def test_fp8_split_limits():
     with pytest.raises(fd.FDError, match="FD_E_UNSUPPORTED"):
         fd.Batch([(plan, r.data_ptr(), z.data_ptr(), 1, plan.N)])
     plan.close()
+
+
+def test_fp64_orders_up_to_224_run_pipelined():
+    _case("FP64 n = 194: every pass, the split last mode included, on the pipelined kernels")
+    fd = _fd()
+    Ks, Ms = _vel_factors((3, 4, 96), 4)  # n = (10, 12, 194)
+    f = FDFactors(Ks, Ms, velocity_weights(3, 2))
+    plan = fd.Plan(Ks, Ms, weights=velocity_weights(3, 2), precision="f64")
+    r = workloads.residuals(31, 2, plan.N)
+    fd.timing_enable(True)
+    try:
+        z = _run_plan(plan, r)
+        fd.timing_read()
+        launches = fd.timing_launches()
+    finally:
+        fd.timing_enable(False)
+    assert launches and all(l["family"] == 3 for l in launches), launches
+    # the last mode (n = 194) runs as two launches in stage 2
+    assert sum(l["count"] for l in launches if l["stage"] == "last_mode_fused") == 2
+    for j in range(r.shape[0]):
+        assert _rel(z[j], fd_apply(f, r[j])) < TOL["f64"]
+    plan.close()
