@@ -109,7 +109,7 @@ def main():
         torch.cuda.set_device(0)
         print(json.dumps({"serving": bench_serve(args, [p for p in args.serve.split(",") if p])}))
         return
-    cfg = workloads.CONFIGS["c2_3d_64_p3"]
+    cfg = workloads.CONFIGS["3d_64_p3_16rhs"]
     prob = cfg["problem"]()
     nrhs, seed = cfg["nrhs"], cfg["seed"]
     torch.cuda.set_device(0)

@@ -69,15 +69,15 @@ def taylor_hood_problem(n_el, p, unit_weights=False):
 # follow from the spaces; they are not stored here.
 CONFIGS = {
     # 2D unit square, 16x16 elements, p = 2, unit-weight velocity sums, FP64, 4 residuals.
-    "c1_2d_16_p2": dict(problem=lambda: taylor_hood_problem((16, 16), 2, unit_weights=True),
-                        nrhs=4, seed=0),
+    "2d_16_p2_4rhs": dict(problem=lambda: taylor_hood_problem((16, 16), 2, unit_weights=True),
+                          nrhs=4, seed=0),
     # 3D unit cube, 64^3 elements, p = 3, paper weights, 16 residuals.
-    "c2_3d_64_p3": dict(problem=lambda: taylor_hood_problem((64, 64, 64), 3), nrhs=16, seed=1),
-    # Config-1 geometry with 64 residuals for the reduced-precision ladder.
-    "c3_2d_16_p2": dict(problem=lambda: taylor_hood_problem((16, 16), 2, unit_weights=True),
-                        nrhs=64, seed=2),
+    "3d_64_p3_16rhs": dict(problem=lambda: taylor_hood_problem((64, 64, 64), 3), nrhs=16, seed=1),
+    # The 2D 16x16 p = 2 patch with 64 residuals for the reduced-precision ladder.
+    "2d_16_p2_64rhs": dict(problem=lambda: taylor_hood_problem((16, 16), 2, unit_weights=True),
+                           nrhs=64, seed=2),
     # Serving large class: 96^3 elements, p = 4.
-    "c5_3d_96_p4": dict(problem=lambda: taylor_hood_problem((96, 96, 96), 4), nrhs=1, seed=4),
+    "3d_96_p4_1rhs": dict(problem=lambda: taylor_hood_problem((96, 96, 96), 4), nrhs=1, seed=4),
 }
 
 

@@ -184,7 +184,7 @@ def test_full_size_64cube_p3(prec):
     """The 64^3, p = 3 block (n_V = 129, n_Q = 67) in the launch configuration of the bench."""
     _case(f"full-size 64^3 p=3 block, prec={prec}")
     from paper_1712_00403_amd.precond import BlockPreconditioner
-    prob = workloads.CONFIGS["c2_3d_64_p3"]["problem"]()
+    prob = workloads.CONFIGS["3d_64_p3_16rhs"]["problem"]()
     pc = BlockPreconditioner(prob, precision=prec)
     assert pc.sizes == [129 ** 3] * 3 + [67 ** 3]
     nrhs = 2
