@@ -343,3 +343,47 @@ def test_fp64_orders_up_to_224_run_pipelined():
     for j in range(r.shape[0]):
         assert _rel(z[j], fd_apply(f, r[j])) < TOL["f64"]
     plan.close()
+
+
+def _random_cases(seed, count):
+    """Seeded 3D/2D blocks with per-direction orders spread over 2..224 (small products)."""
+    rng = np.random.default_rng(seed)
+    cases = []
+    for _ in range(count):
+        d = int(rng.integers(2, 4))
+        big = int(rng.integers(0, d))
+        n = []
+        for i in range(d):
+            if i == big:
+                n.append(int(rng.integers(2, 225)))
+            else:
+                n.append(int(rng.integers(2, 24 if d == 3 else 60)))
+        cases.append(tuple(n))
+    return cases
+
+
+def _spd_pair(n, rng):
+    """A random SPD pencil (K, M) of order n: M diagonally dominant, K = A A^T + n I."""
+    A = rng.standard_normal((n, n))
+    M = np.eye(n) * n + 0.1 * (A + A.T)
+    B = rng.standard_normal((n, n))
+    K = B @ B.T + n * np.eye(n)
+    return K, M
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f16", "fp8_split"])
+@pytest.mark.parametrize("shape", _random_cases(2024, 8))
+def test_random_orders(prec, shape):
+    _case(f"random-order block n={shape} prec={prec}")
+    rng = np.random.default_rng(sum(shape) * 7 + len(shape))
+    pairs = [_spd_pair(n, rng) for n in shape]
+    Ks, Ms = [p[0] for p in pairs], [p[1] for p in pairs]
+    w = rng.uniform(0.5, 2.0, len(shape))
+    f = FDFactors(Ks, Ms, w)
+    plan = _fd().Plan(Ks, Ms, weights=w, precision=prec)
+    r = workloads.residuals(int(rng.integers(0, 1000)), 2, plan.N)
+    z = _run_plan(plan, r)
+    for j in range(r.shape[0]):
+        err = _rel(z[j], fd_apply(f, r[j]))
+        assert err < TOL[prec], f"residual {j}: rel err {err:.3e}"
+    plan.close()
