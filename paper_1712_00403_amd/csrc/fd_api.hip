@@ -382,8 +382,11 @@ static fd_status batch_build_layout(fd_batch_s* b, int choice) {
       bd.u.tiles_per_rhs = int32_t((NQ + chunk - 1) / chunk);
       passes.emplace_back(body, bd);
     }
+    // segments of a stage run one after another on every workgroup: the
+    // largest row-tile counts first, so that the tiles left when workgroups
+    // reach the stage's barrier are the cheapest ones
     auto key = [](const std::pair<int, fdk::BatchDesc>& x) {
-      return std::make_tuple(x.first, x.second.mode, x.second.mt, x.second.scale);
+      return std::make_tuple(-x.second.mt, x.first, x.second.mode, x.second.scale);
     };
     std::stable_sort(passes.begin(), passes.end(), [&](const auto& x, const auto& y) { return key(x) < key(y); });
     int64_t t = 0;
