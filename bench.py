@@ -12,6 +12,7 @@ oracle itself is timed on the host cores as `cpu_baseline`.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--precisions f64,f32,...]
 """
 import argparse
+import gc
 import json
 import os
 import sys
@@ -387,9 +388,16 @@ def bench_serve(args, precisions):
             srv.step()
             srv.collect(wait=True)
         torch.cuda.synchronize()
+        # no garbage-collector pauses inside the timed stream (a serving
+        # process collects between bursts)
+        gc.collect()
+        gc.disable()
         t0 = time.perf_counter()
         ex.t0, ex.ev_ref = t0, None
-        reqs = serve.run_stream(srv, arrivals, lambda: time.perf_counter() - t0, {k: 4 for k in problems})
+        try:
+            reqs = serve.run_stream(srv, arrivals, lambda: time.perf_counter() - t0, {k: 4 for k in problems})
+        finally:
+            gc.enable()
         summ = serve.latency_summary(reqs, args.serve_seconds)
         summ.update({"steps": srv.steps, "plan_cache_bytes": srv.cache.bytes, "evictions": srv.cache.evictions,
                      "offered_dof_per_s": sum(r.dofs for r in reqs) / args.serve_seconds})
