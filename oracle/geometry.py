@@ -179,11 +179,23 @@ def kron_diag(diags):
     return out
 
 
+def tensor_grid(axes):
+    """Every point of the tensor grid of the 1D point arrays ``axes`` as rows (P, d), axis 1 fastest."""
+    d = len(axes)
+    sizes = [len(a) for a in axes]
+    P = int(np.prod(sizes))
+    pts = np.empty((P, d))
+    for j, a in enumerate(axes):
+        inner = int(np.prod(sizes[:j]))          # points of the faster axes
+        outer = P // (inner * sizes[j])
+        pts[:, j] = np.tile(np.repeat(np.asarray(a, dtype=np.float64), inner), outer)
+    return pts
+
+
 def _grid_fields(geometry, n_el, npts):
     """J and nu on the tensor quadrature grid (axis 1 fastest)."""
-    from paper_1712_00403_amd.workloads import tensor_points
     axes = [x for x, _ in grid_axes(n_el, npts)]
-    eta = tensor_points(axes)
+    eta = tensor_grid(axes)
     J = geometry.jacobian(eta)
     nu = geometry.nu(geometry.map(eta))
     shape = tuple(len(a) for a in axes)

@@ -231,6 +231,7 @@ class Plan:
         h = ctypes.c_void_p(0)
         _check(L.fd_setup(ndim, narr, Karr, Marr, _dp(w), _dp(dt), self.prec_id, ctypes.byref(h)))
         self.handle = h.value
+        self.device = _current_device()
         self.N = int(L.fd_plan_size(self.handle))
         self.device_bytes = int(L.fd_plan_device_bytes(self.handle))
 
@@ -252,13 +253,11 @@ class Plan:
     def apply(self, r, z=None, stream=None):
         """z = P^{-1} r for a torch device tensor r of shape (nrhs, N) or (N,)."""
         import torch
-        if r.dtype != getattr(torch, self.io_dtype):
-            raise TypeError(f"plan expects {self.io_dtype} vectors")
         if z is None:
+            check_vectors(r, None, self.N, self.io_dtype, self.device)
             z = torch.empty_like(r)
+        check_vectors(r, z, self.N, self.io_dtype, self.device)
         r2 = r.reshape(-1, r.shape[-1])
-        if r2.shape[-1] < self.N or r.stride(-1) != 1:
-            raise ValueError("vectors must be contiguous with at least N entries")
         nrhs = r2.shape[0]
         ld = r2.stride(0) if nrhs > 1 else r2.shape[-1]
         s = _stream_handle(stream)
@@ -275,6 +274,45 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def _current_device():
+    """The current HIP device (the device fd_setup places a plan on) as a torch.device."""
+    import torch
+    return torch.device("cuda", torch.cuda.current_device())
+
+
+def check_vectors(r, z, N, io_dtype, device, exact=False):
+    """Reject vectors the library would read or write out of bounds, before any pointer is passed.
+
+    r (and z unless None) must be tensors on ``device`` (a torch.device) with dtype
+    ``io_dtype``, of shape (nrhs, L) or (L,) with unit stride along the last
+    axis and L >= N (L == N and contiguous if ``exact``); z must have r's
+    shape and strides. Raises TypeError for a wrong dtype, ValueError
+    otherwise.
+    """
+    import torch
+    want = getattr(torch, io_dtype)
+    for name, t in (("r", r), ("z", z)):
+        if t is None:
+            continue
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.dtype != want:
+            raise TypeError(f"{name} has dtype {t.dtype}; the plan expects {io_dtype} vectors")
+        if t.device != device:
+            raise ValueError(f"{name} is on {t.device}; the plan lives on {device}")
+        if t.dim() not in (1, 2):
+            raise ValueError(f"{name} must have shape (nrhs, L) or (L,)")
+        if t.stride(-1) != 1 or (t.dim() == 2 and t.shape[0] > 1 and t.stride(0) < t.shape[-1]):
+            raise ValueError(f"{name} must have unit stride along its last axis and non-overlapping rows")
+        if exact and (t.shape[-1] != N or not t.is_contiguous()):
+            raise ValueError(f"{name} must be contiguous with exactly {N} entries per vector")
+        if t.shape[-1] < N:
+            raise ValueError(f"{name} has {t.shape[-1]} entries per vector; the plan needs {N}")
+    if z is not None and (tuple(z.shape) != tuple(r.shape) or z.stride() != r.stride()):
+        raise ValueError(f"z must have r's shape and strides (r {tuple(r.shape)}/{r.stride()}, "
+                         f"z {tuple(z.shape)}/{z.stride()})")
 
 
 def _stream_handle(stream):

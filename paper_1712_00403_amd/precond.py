@@ -57,13 +57,12 @@ class BlockPreconditioner:
     def apply(self, r, z=None, stream=None):
         """z = P_D^{-1} r for a torch device tensor of shape (nrhs, N_block) or (N_block,)."""
         import torch
-        if r.dtype != getattr(torch, self.io_dtype):
-            raise TypeError(f"preconditioner expects {self.io_dtype} vectors")
+        dev = self.plans[0].device
         if z is None:
+            fd.check_vectors(r, None, self.N, self.io_dtype, dev, exact=True)
             z = torch.empty_like(r)
+        fd.check_vectors(r, z, self.N, self.io_dtype, dev, exact=True)
         r2 = r.reshape(-1, r.shape[-1])
-        if r2.shape[-1] != self.N or not r.is_contiguous() or not z.is_contiguous():
-            raise ValueError("block vectors must be contiguous with N_block entries")
         fd.apply_batched(self.works(r.data_ptr(), z.data_ptr(), r2.shape[0]), stream)
         return z
 

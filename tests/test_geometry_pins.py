@@ -222,3 +222,12 @@ def test_geometry_block_apply_matches_brute_force_solve():
     assert _rel(z[off:], zq) < 1e-12
     # the scaling is not trivial here
     assert np.max(np.abs(gb.vel_scales[0] - 1.0)) > 1e-3
+
+
+def test_tensor_grid_order_matches_nested_loops():
+    """The oracle's quadrature grid lists points with axis 1 fastest (brute force on a tiny grid)."""
+    from oracle.geometry import tensor_grid
+    ax = [np.array([0.1, 0.2]), np.array([1.0, 2.0, 3.0]), np.array([7.0, 8.0])]
+    expect = [(a, b, c) for c in ax[2] for b in ax[1] for a in ax[0]]
+    assert np.array_equal(tensor_grid(ax), np.array(expect))
+    assert np.array_equal(tensor_grid(ax[:2]), np.array([(a, b) for b in ax[1] for a in ax[0]]))

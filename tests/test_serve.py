@@ -21,9 +21,10 @@ class VirtualExecutor:
         self.sizes, self.plan_bytes = sizes, plan_bytes
         self.base, self.per_dof = base, per_dof
         self.now = 0.0
-        self.busy_until = 0.0
+        self.busy_until = {}
         self.builds = []
         self.launched = []
+        self.lanes = []
 
     def build(self, rc):
         self.builds.append(rc.name)
@@ -32,11 +33,13 @@ class VirtualExecutor:
     def io_bytes(self, pc):
         return 4 * pc.N
 
-    def launch(self, items):
-        start = max(self.now, self.busy_until)
-        self.busy_until = start + self.base + self.per_dof * sum(pc.N for pc, _ in items)
+    def launch(self, items, lane=0):
+        # lanes run concurrently on the virtual device; steps of one lane in order
+        start = max(self.now, self.busy_until.get(lane, 0.0))
+        self.busy_until[lane] = start + self.base + self.per_dof * sum(pc.N for pc, _ in items)
         self.launched.append([r.rid for _, r in items])
-        return self.busy_until
+        self.lanes.append(lane)
+        return self.busy_until[lane]
 
     def finished(self, handle, wait):
         if wait or handle <= self.now:
@@ -44,8 +47,9 @@ class VirtualExecutor:
         return None
 
 
-def _classes(names):
-    return {k: serve.RequestClass(k, None, "f32") for k in names}
+def _classes(names, lanes=None):
+    lanes = lanes or {}
+    return {k: serve.RequestClass(k, None, "f32", lanes.get(k, 0)) for k in names}
 
 
 def test_continuous_batching_and_latency():
@@ -110,7 +114,67 @@ def test_step_respects_io_budget():
     for i in range(3):
         srv.submit(serve.Request(i, "a", 0.0))
     assert srv.step() == 2
+    # the results of the step in flight still hold 800 B: the third request waits
+    assert srv.step() == 0
+    assert srv.waits == 1
+    ex.now = 1.0
     assert srv.step() == 1
+
+
+def test_blocked_class_evicts_classes_with_pending_requests():
+    # a and b cached (400 B each, budget 1000); a burst c, a, b: c must evict an
+    # idle class although a and b have requests queued behind it
+    ex = VirtualExecutor({"a": 10, "b": 10, "c": 10}, {"a": 400, "b": 400, "c": 400})
+    srv = serve.Server(_classes(["a", "b", "c"]), ex, hbm_budget=1000)
+    for i, c in enumerate(["a", "b"]):
+        srv.submit(serve.Request(i, c, 0.0))
+        srv.step()
+        srv.collect(wait=True)
+    assert list(srv.cache.entries) == ["a", "b"]
+    for i, c in enumerate(["c", "a", "b"]):
+        srv.submit(serve.Request(10 + i, c, 0.0))
+    while srv.pending or srv.inflight:
+        srv.step()
+        ex.now += 1.0
+        srv.collect()
+    assert all(r.done is not None for r in srv.done)
+    assert sorted(r.rid for r in srv.done) == [0, 1, 10, 11, 12]
+    assert srv.cache.bytes <= 1000
+    assert srv.cache.evictions >= 1
+
+
+def test_class_bytes_are_remembered_no_rebuild_while_waiting():
+    # b (600 B) cannot be admitted while a step of a (400 B) is in flight:
+    # it is built once, refused, and later admitted without a rebuild attempt per retry
+    ex = VirtualExecutor({"a": 10, "b": 10}, {"a": 400, "b": 600})
+    srv = serve.Server(_classes(["a", "b"]), ex, hbm_budget=900)
+    srv.submit(serve.Request(0, "a", 0.0))
+    assert srv.step() == 1
+    srv.submit(serve.Request(1, "b", 0.0))
+    for _ in range(5):
+        assert srv.step() == 0
+    assert ex.builds == ["a", "b"]
+    ex.now = 1.0
+    assert srv.step() == 1
+    assert ex.builds == ["a", "b", "b"]
+    assert srv.cache.evictions == 1
+
+
+def test_lanes_do_not_block_each_other():
+    # a slow class in lane 1 and a fast class in lane 0: the fast requests run
+    # beside the slow step, not behind it
+    ex = VirtualExecutor({"small": 10, "big": 10 ** 7}, {"small": 10, "big": 10}, base=1e-4, per_dof=1e-9)
+    srv = serve.Server(_classes(["small", "big"], {"small": 0, "big": 1}), ex, hbm_budget=10 ** 9,
+                       max_inflight=1)
+    srv.submit(serve.Request(0, "big", 0.0))
+    srv.submit(serve.Request(1, "small", 0.0))
+    assert srv.step() == 2
+    assert ex.lanes == [0, 1] and ex.launched == [[1], [0]]
+    srv.collect(wait=True)
+    small = next(r for r in srv.done if r.cls == "small")
+    big = next(r for r in srv.done if r.cls == "big")
+    assert small.done == pytest.approx(1e-4 + 1e-8)
+    assert big.done > 1e-2
 
 
 def test_poisson_arrivals_rate_and_mix():
