@@ -5,9 +5,15 @@ One step = z = P_D^{-1} r for 16 synthetic Gaussian residual block vectors
 per residual), every pass of Algorithm 1 on the GPU, inputs resident in HBM.
 
 The headline `value` is the FP64 path (the paper's precision). The same
-workload is also timed in FP32, BF16 and BF16-split (the precision ladder),
-each with its relative error against the FP64 oracle on residual 0. The
-oracle itself is timed on the host cores as `cpu_baseline`.
+workload is also timed in every other precision class (the precision ladder),
+each with its per-block relative errors (2-norm and element-wise) against the
+FP64 oracle on every residual. The oracle itself is timed on the host cores
+(all threads: `cpu_baseline`; one thread beside it).
+
+Further legs: the 2D 16x16 p = 2 patch (microseconds per apply in FP64, 4
+residuals; 64-residual batches in the reduced precisions with the
+per-residual error distribution), the 256-patch coefficient-aware batch in
+one persistent launch, and the Poisson serving stream.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--precisions f64,f32,...]
 """
@@ -26,7 +32,8 @@ sys.path.insert(0, ROOT)
 METRIC = "FD applies/s & DOF/s, 3D p=3 64^3 elem; mixed vs FP64 at rel-err; p50/p99 latency"
 # sources the dominant kernel is built from: HBM traffic counters recorded in
 # profiles/ count only while these files are unchanged
-KERNEL_SOURCES = ["fd_pass3.inc", "fd_pass2.inc", "fd_pass.inc", "fd_internal.h", "fd_pass_f64.hip", "fd_pass_f32.hip"]
+KERNEL_SOURCES = ["fd_pass3.inc", "fd_pass2.inc", "fd_pass.inc", "fd_internal.h", "fd_pass_f64.hip", "fd_pass_f32.hip",
+                  "fd_api.hip", "fd_kernels.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fd_pass3_fused_64cube_p3_traffic.json")
 PEAKS = {"f64": 78.6e12, "f32": 157.3e12, "bf16": 2.5e15, "bf16_split": 2.5e15, "f16": 2.5e15,
          "f16_split": 2.5e15, "fp8_split": 5.0e15}
@@ -87,9 +94,11 @@ def main():
                     help="precisions of the 256-patch persistent batch leg ('' to skip)")
     ap.add_argument("--batch-patches", type=int, default=256)
     ap.add_argument("--batch-only", action="store_true", help="run only the persistent batch leg")
-    ap.add_argument("--serve-seconds", type=float, default=8.0, help="length of each serving run (0 to skip)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="length of each serving run (0 to skip)")
     ap.add_argument("--serve", default="f64,bf16", help="precisions of the serving runs")
     ap.add_argument("--serve-only", action="store_true")
+    ap.add_argument("--small", default="f64,f32,bf16,f16,bf16_split,f16_split,fp8_split",
+                    help="precisions of the 2D 16x16 legs ('' to skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -125,13 +134,18 @@ def main():
     sizes = [(129, 129, 129)] * 3 + [(67, 67, 67)]
     assert ref.sizes == [int(np.prod(s)) for s in sizes]
     N = ref.N
+    offs = ref.offsets
     log(f"block size {N}, {nrhs} residuals, seed {seed}")
     r_host = workloads.residuals(seed, nrhs, N)
     flops_apply = algorithmic_flops(sizes)
 
+    # the oracle's block vectors of every residual (checked against every
+    # precision), timed on all host threads as the CPU baseline
+    zo_all, cpu = None, None
+    if not args.only:
+        zo_all, cpu = oracle_c2(args, r_host)
+
     results = {}
-    z0 = {}
-    stream = torch.cuda.current_stream()
     for p in precisions:
         pc = pcs[p]
         dt = torch.float64 if pc.io_dtype == "float64" else torch.float32
@@ -146,7 +160,11 @@ def main():
         torch.cuda.synchronize()
         dt_s = time.perf_counter() - t0
         ms = dt_s * 1e3 / args.steps
-        z0[p] = z[0].double().cpu().numpy()
+        errs = None
+        if zo_all is not None:
+            zh = z.double().cpu().numpy()
+            errs = block_errors(zh, zo_all, offs)
+            del zh
         # per-stage kernel time, measured with HIP events on the launch stream
         fd.timing_enable(True)
         for _ in range(args.steps):
@@ -159,46 +177,15 @@ def main():
         dom = [c for c in launches if c["stage"] == "last_mode_fused" and c["n"] == 129]
         dom_ms = dom[0]["ms"] / dom[0]["count"]
         applies = nrhs / (ms * 1e-3)
-        results[p] = {"dominant_ms": dom_ms, "launches": launches,"ms_per_step": ms, "applies_per_s": applies, "dof_per_s": applies * N,
-                      "tflops": flops_apply * applies / 1e12,
+        results[p] = {"dominant_ms": dom_ms, "launches": launches, "ms_per_step": ms, "applies_per_s": applies,
+                      "dof_per_s": applies * N, "tflops": flops_apply * applies / 1e12, "errors": errs,
                       "stage_ms": {k: v[0] / max(v[1], 1) for k, v in stages.items()}}
-        log(f"{p}: {ms:.3f} ms/step, {applies:.1f} applies/s, {results[p]['tflops']:.2f} TFLOP/s")
+        msg = f"{p}: {ms:.3f} ms/step, {applies:.1f} applies/s, {results[p]['tflops']:.2f} TFLOP/s"
+        if errs:
+            msg += f", max rel err {errs['rel_err_max']:.2e}, max rel elementwise err {errs['rel_maxnorm_err_max']:.2e}"
+        log(msg)
         del r, z
         torch.cuda.empty_cache()
-
-    # relative error of residual 0 against the FP64 oracle, per block
-    log("oracle check of residual 0")
-    from oracle.assemble import pressure_1d, taylor_hood_velocity_1d
-    from oracle.fd import FDFactors, block_apply, velocity_weights
-    t0 = time.perf_counter()
-    Kv, Mv = taylor_hood_velocity_1d(64, 3)
-    facs = [FDFactors([Kv] * 3, [Mv] * 3, velocity_weights(3, k)) for k in range(3)]
-    Mp = [pressure_1d(64, 3)] * 3
-    oracle_setup = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    zo = block_apply(facs, Mp, r_host[0])
-    t_first = time.perf_counter() - t0
-    offs = ref.offsets
-    for p in precisions:
-        errs = [float(np.linalg.norm(z0[p][a:b] - zo[a:b]) / np.linalg.norm(zo[a:b]))
-                for a, b in zip(offs[:-1], offs[1:])]
-        results[p]["rel_err_blocks"] = errs
-        results[p]["rel_err_max"] = max(errs)
-
-    cpu = None
-    if not args.no_cpu:
-        import threadpoolctl
-        threads = max([i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()] or [1])
-        done, t_cpu = 1, t_first
-        while done < nrhs and t_cpu < args.cpu_seconds:
-            t0 = time.perf_counter()
-            block_apply(facs, Mp, r_host[done])
-            t_cpu += time.perf_counter() - t0
-            done += 1
-        cpu = {"value": done / t_cpu, "unit": "applies/s", "cores": int(threads), "kind": "oracle",
-               "sample": f"{done} of the {nrhs} residuals of one step (full 64^3 p=3 block apply each, "
-                         f"numpy FP64, steps 2-4 of Algorithm 1 plus banded pressure solves; "
-                         f"oracle setup {oracle_setup:.1f} s excluded)"}
 
     head = results["f64"] if "f64" in results else results[precisions[0]]
     head_prec = "f64" if "f64" in results else precisions[0]
@@ -217,15 +204,25 @@ def main():
                 "algorithmic_bytes_per_launch": nrhs * 3 * 129 ** 3 * (16 if head_prec == "f64" else 8),
                 "kernel_source_hash": kernel_source_hash()}
 
-    ladder = {p: {"applies_per_s": round(v["applies_per_s"], 2), "dof_per_s": v["dof_per_s"],
-                  "ms_per_step": round(v["ms_per_step"], 4), "tflops": round(v["tflops"], 2),
-                  "frac_of_peak": v["tflops"] * 1e12 / PEAKS[p],
-                  "rel_err_max": v["rel_err_max"], "rel_err_blocks": v["rel_err_blocks"],
-                  "speedup_vs_f64": (v["applies_per_s"] / results["f64"]["applies_per_s"]
-                                     if "f64" in results else None),
-                  "stage_ms": {k: round(x, 4) for k, x in v["stage_ms"].items()},
-                  "dominant_kernel_ms": round(v["dominant_ms"], 4)}
-              for p, v in results.items()}
+    ladder = {}
+    for p, v in results.items():
+        e = v["errors"] or {}
+        ladder[p] = {"applies_per_s": round(v["applies_per_s"], 2), "dof_per_s": v["dof_per_s"],
+                     "ms_per_step": round(v["ms_per_step"], 4), "tflops": round(v["tflops"], 2),
+                     "frac_of_peak": v["tflops"] * 1e12 / PEAKS[p],
+                     "hbm_frac_of_peak": v["applies_per_s"] * N * (16 if p == "f64" else 8) / HBM_PEAK,
+                     "rel_err_max": e.get("rel_err_max"), "rel_maxnorm_err_max": e.get("rel_maxnorm_err_max"),
+                     "rel_err_blocks": e.get("rel_err_blocks"), "rel_maxnorm_err_blocks": e.get("rel_maxnorm_err_blocks"),
+                     "speedup_vs_f64": (v["applies_per_s"] / results["f64"]["applies_per_s"]
+                                        if "f64" in results else None),
+                     "stage_ms": {k: round(x, 4) for k, x in v["stage_ms"].items()},
+                     "dominant_kernel_ms": round(v["dominant_ms"], 4)}
+    for pc in pcs.values():
+        pc.close()
+    del zo_all
+    small = None
+    if args.small and not args.only:
+        small = bench_small(args, [p for p in args.small.split(",") if p])
     batch = None
     if args.batch and not args.only:
         batch = bench_batch(args, [p for p in args.batch.split(",") if p])
@@ -240,12 +237,129 @@ def main():
            "config": {"workload": "3D unit cube 64^3 elements, Taylor-Hood p=3 (velocity degree 4, "
                                   "n_V=129, pressure n_Q=67), full block P_D^-1, 16 Gaussian residuals seed 1",
                       "global_batch": nrhs, "dofs_per_residual": N, "parallelism": "single GPU"},
-           "dof_per_s": head["dof_per_s"], "rel_err_vs_oracle": head["rel_err_max"],
+           "dof_per_s": head["dof_per_s"],
+           "rel_err_vs_oracle": (head["errors"] or {}).get("rel_err_max"),
+           "rel_maxnorm_err_vs_oracle": (head["errors"] or {}).get("rel_maxnorm_err_max"),
            "plan_setup_s": round(setup_s, 3), "roofline": roofline, "cpu_baseline": cpu,
-           "ladder": ladder, "batch_256_patches": batch, "serving": serving}
+           "ladder": ladder, "small_2d_16_p2": small, "batch_256_patches": batch, "serving": serving}
     print(json.dumps(out))
-    for pc in pcs.values():
-        pc.close()
+
+
+def block_errors(zh, zo_all, offs):
+    """Per residual and block: relative 2-norm and relative max-norm errors against the oracle."""
+    e2 = np.zeros((zh.shape[0], len(offs) - 1))
+    em = np.zeros_like(e2)
+    for j in range(zh.shape[0]):
+        for k, (a, b) in enumerate(zip(offs[:-1], offs[1:])):
+            d = zh[j, a:b] - zo_all[j][a:b]
+            e2[j, k] = np.linalg.norm(d) / np.linalg.norm(zo_all[j][a:b])
+            em[j, k] = np.max(np.abs(d)) / np.max(np.abs(zo_all[j][a:b]))
+    return {"rel_err_max": float(e2.max()), "rel_maxnorm_err_max": float(em.max()),
+            "rel_err_blocks": [float(x) for x in e2.max(axis=0)],
+            "rel_maxnorm_err_blocks": [float(x) for x in em.max(axis=0)],
+            "rel_err_per_residual": [float(x) for x in e2.max(axis=1)]}
+
+
+def oracle_c2(args, r_host):
+    """Oracle block vectors of every residual of the 64^3 p = 3 workload, and the CPU baseline timings.
+
+    All host threads: the whole batch (also the reference values of the
+    ladder). One thread: a bounded sample of residuals, beside it.
+    """
+    import threadpoolctl
+
+    from oracle.assemble import pressure_1d, taylor_hood_velocity_1d
+    from oracle.fd import FDFactors, block_apply, velocity_weights
+    log("oracle: setup and every residual on all host threads")
+    t0 = time.perf_counter()
+    Kv, Mv = taylor_hood_velocity_1d(64, 3)
+    facs = [FDFactors([Kv] * 3, [Mv] * 3, velocity_weights(3, k)) for k in range(3)]
+    Mp = [pressure_1d(64, 3)] * 3
+    oracle_setup = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()] or [1])
+    t0 = time.perf_counter()
+    zo_all = [block_apply(facs, Mp, r_host[j]) for j in range(r_host.shape[0])]
+    t_all = time.perf_counter() - t0
+    cpu = None
+    if not args.no_cpu:
+        cpu = {"value": r_host.shape[0] / t_all, "unit": "applies/s", "cores": int(threads), "kind": "oracle",
+               "sample": f"all {r_host.shape[0]} residuals of one step (full 64^3 p=3 block apply each, numpy FP64, "
+                         f"steps 2-4 of Algorithm 1 plus banded pressure solves; oracle setup "
+                         f"{oracle_setup:.1f} s excluded)", "cpu": cpu_model()}
+        done, t1 = 0, 0.0
+        with threadpoolctl.threadpool_limits(1):
+            while done < r_host.shape[0] and t1 < args.cpu_seconds:
+                t0 = time.perf_counter()
+                block_apply(facs, Mp, r_host[done])
+                t1 += time.perf_counter() - t0
+                done += 1
+        cpu["one_thread"] = {"value": done / t1, "unit": "applies/s", "cores": 1,
+                             "sample": f"{done} residuals, BLAS limited to one thread"}
+        log(f"oracle: {cpu['value']:.2f} applies/s on {threads} threads, {cpu['one_thread']['value']:.3f} on one")
+    return zo_all, cpu
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def bench_small(args, precisions):
+    """The 2D 16x16, p = 2 Taylor-Hood patch (n_V = 32, n_Q = 18): launch-latency bound.
+
+    FP64 with 4 residuals (seed 0): microseconds per step and per residual
+    apply. Every precision with 64 residuals (seed 2): microseconds per
+    64-residual batch, and the distribution over residuals of the largest
+    per-block relative error against the oracle.
+    """
+    import torch
+
+    from oracle.assemble import pressure_1d, taylor_hood_velocity_1d
+    from oracle.fd import FDFactors, block_apply
+    from paper_1712_00403_amd import workloads
+    from paper_1712_00403_amd.precond import BlockPreconditioner
+    Kv, Mv = taylor_hood_velocity_1d(16, 2)
+    facs = [FDFactors([Kv] * 2, [Mv] * 2) for _ in range(2)]
+    Mp = [pressure_1d(16, 2)] * 2
+    out = {"workload": "2D unit square 16x16 elements, Taylor-Hood p=2 (n_V=32, n_Q=18), unit-weight velocity "
+                       "blocks, 2372 DOFs per block vector", "legs": {}}
+    reps = max(args.steps, 10) * 20
+    for name, key, precs in (("fp64_4rhs", "2d_16_p2_4rhs", ["f64"]), ("ladder_64rhs", "2d_16_p2_64rhs", precisions)):
+        cfg = workloads.CONFIGS[key]
+        prob = cfg["problem"]()
+        leg = {"nrhs": cfg["nrhs"], "seed": cfg["seed"], "precisions": {}}
+        for p in precs:
+            pc = BlockPreconditioner(prob, precision=p)
+            r_host = workloads.residuals(cfg["seed"], cfg["nrhs"], pc.N)
+            zo = [block_apply(facs, Mp, r_host[j]) for j in range(cfg["nrhs"])]
+            dt = torch.float64 if pc.io_dtype == "float64" else torch.float32
+            r = torch.from_numpy(r_host).to(dt).cuda()
+            z = torch.empty_like(r)
+            for _ in range(args.warmup * 10):
+                pc.apply(r, z)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                pc.apply(r, z)
+            torch.cuda.synchronize()
+            us = (time.perf_counter() - t0) * 1e6 / reps
+            e = block_errors(z.double().cpu().numpy(), zo, pc.offsets)
+            per = np.array(e["rel_err_per_residual"])
+            leg["precisions"][p] = {"us_per_step": round(us, 2), "us_per_residual_apply": round(us / cfg["nrhs"], 3),
+                                    "rel_err_max": e["rel_err_max"], "rel_maxnorm_err_max": e["rel_maxnorm_err_max"],
+                                    "rel_err_per_residual_quantiles": {
+                                        "min": float(per.min()), "p50": float(np.median(per)),
+                                        "p90": float(np.percentile(per, 90)), "max": float(per.max())}}
+            log(f"2D 16^2 {name} {p}: {us:.1f} us per {cfg['nrhs']}-residual step, rel err max {e['rel_err_max']:.2e}")
+            pc.close()
+        out["legs"][name] = leg
+    return out
 
 
 def bench_batch(args, precisions):
@@ -277,7 +391,7 @@ def bench_batch(args, precisions):
     geo = workloads.sine_geometry(3)
     probs = [workloads.taylor_hood_problem(n_el, p, unit_weights=True) for n_el, p in patches]
     t0 = time.perf_counter()
-    with ThreadPoolExecutor(max_workers=4) as ex:
+    with ThreadPoolExecutor(max_workers=16) as ex:
         blocks = list(ex.map(lambda pr: geometry_blocks(pr, geo), probs))
     setup_s = time.perf_counter() - t0
     log(f"batch: host setup of {len(probs)} patches {setup_s:.1f} s")
@@ -312,6 +426,7 @@ def bench_batch(args, precisions):
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / args.steps
         b.check()
+        Zp = Z.double().cpu().numpy()   # the persistent launch's result, checked below
         # the same works through per-stage grouped launches, for comparison
         for _ in range(args.warmup):
             fd.apply_batched(works)
@@ -323,34 +438,26 @@ def bench_batch(args, precisions):
         ms_grouped = (time.perf_counter() - t0) * 1e3 / args.steps
         dofs = int(offs[-1])
         passes = sum(len(pc.problem.blocks) for pc in pcs)
-        # algorithmic bytes: every pass reads and writes the block once; the
-        # scaled blocks read D^{-1/2} twice
-        byts = sum(5 * 2 * N * eb + 2 * N * eb for N in [p.N for pc in pcs for p in pc.plans])
+        # algorithmic bytes of one apply: every block read once and written
+        # once, and its D^{-1/2} read twice (before the first and after the
+        # last product); what the five passes move is reported beside it
+        alg_bytes = dofs * (2 * eb + 2 * eb)
+        pass_bytes = 5 * 2 * dofs * eb + 2 * dofs * eb
         out["precisions"][prec] = {"ms_per_apply": round(ms, 4), "dof_per_s": dofs / (ms * 1e-3),
                                    "patch_applies_per_s": len(pcs) / (ms * 1e-3),
-                                   "algorithmic_gb_per_s": byts / (ms * 1e-3) / 1e9,
+                                   "algorithmic_gb_per_apply": alg_bytes / 1e9,
+                                   "algorithmic_gb_per_s": alg_bytes / (ms * 1e-3) / 1e9,
+                                   "hbm_frac_of_peak": alg_bytes / (ms * 1e-3) / HBM_PEAK,
+                                   "five_pass_gb_per_s": pass_bytes / (ms * 1e-3) / 1e9,
                                    "ms_per_apply_grouped_launches": round(ms_grouped, 4),
                                    "launches_per_apply": 1, "tiles": info["tiles"], "grid": info["grid"],
                                    "tuned_config": config, "dofs": dofs, "blocks": passes}
         log(f"batch {prec}: {ms:.3f} ms/apply (one launch; grouped launches {ms_grouped:.3f} ms), "
-            f"{dofs / (ms * 1e-3) / 1e9:.2f} GDOF/s")
-        # oracle check of the three smallest patches
-        from oracle.fd import FDFactors, block_apply
-        from oracle.geometry import GeometryBlocks
-        small = sorted(range(len(pcs)), key=lambda i: sizes[i])[:3]
-        errs = []
-        zh = Z.double().cpu().numpy()
-        for i in small:
-            n_el, p = patches[i]
-            gb = GeometryBlocks(n_el, p, geo)
-            facs = [FDFactors(gb.vel_K[k], gb.vel_M[k]) for k in range(3)]
-            zo = block_apply(facs, gb.pres_M, res[i], pres_scale=gb.pres_scale, vel_scales=gb.vel_scales)
-            zi = zh[offs[i]:offs[i + 1]]
-            po = pcs[i].offsets
-            errs.append(max(float(np.linalg.norm(zi[a:c] - zo[a:c]) / np.linalg.norm(zo[a:c]))
-                            for a, c in zip(po[:-1], po[1:])))
-        out["precisions"][prec]["rel_err_max_sampled"] = max(errs)
-        out["precisions"][prec]["sampled_patches"] = [list(patches[i][0]) + [patches[i][1]] for i in small]
+            f"{dofs / (ms * 1e-3) / 1e9:.2f} GDOF/s, {alg_bytes / (ms * 1e-3) / 1e9:.0f} GB/s algorithmic")
+        # oracle values at sampled pencils of the 8 largest and 8 drawn patches
+        # (computed by tests/golden/make_batch_golden.py from the oracle alone)
+        out["precisions"][prec].update(batch_sample_errors(Zp, offs, pcs, patches, prec))
+        del Zp
         b.close()
         for pc in pcs:
             pc.close()
@@ -359,24 +466,53 @@ def bench_batch(args, precisions):
     return out
 
 
+def batch_sample_errors(Zh, offs, pcs, patches, prec):
+    """Sampled relative errors (RMS and element-wise) of the checked patches against the stored oracle values."""
+    gdir = os.path.join(ROOT, "tests", "golden")
+    path = os.path.join(gdir, "batch_256_sampled.npz")
+    if not os.path.exists(path) or len(pcs) != 256:
+        return {"rel_err_max_sampled": None}
+    golden = dict(np.load(path))
+    e2m, emm, checked = 0.0, 0.0, []
+    for i in golden["patches"]:
+        zi = Zh[offs[i]:offs[i + 1]]
+        po = pcs[i].offsets
+        for b in range(len(po) - 1):
+            zb = zi[po[b]:po[b + 1]]
+            d = zb[golden[f"p{i}_b{b}_idx"]] - golden[f"p{i}_b{b}_val"]
+            e2m = max(e2m, float(np.sqrt(np.mean(d * d)) / golden[f"p{i}_b{b}_rms"]))
+            emm = max(emm, float(np.max(np.abs(d)) / golden[f"p{i}_b{b}_max"]))
+        checked.append(list(patches[int(i)][0]) + [patches[int(i)][1]])
+    log(f"batch {prec}: sampled rel err {e2m:.2e}, rel max err {emm:.2e} over {len(checked)} patches")
+    return {"rel_err_max_sampled": e2m, "rel_maxnorm_err_max_sampled": emm,
+            "sampled_patches": checked,
+            "sample": "8 largest and 8 drawn patches, whole pencils per direction of every block"}
+
+
 def bench_serve(args, precisions):
     """Poisson stream of FD-apply requests of mixed sizes through the continuous-batching server.
 
     2000 requests/s (seed 4): 70% 2D 16x16 p = 2 block vectors, 25% 3D 64^3
-    p = 3, 5% 3D 96^3 p = 4; residuals from a seeded device pool per class;
-    factors cached on the device under an HBM budget; latency = completion
-    (HIP event on the launch stream) minus arrival.
+    p = 3, 5% 3D 96^3 p = 4, each class in a lane (HIP stream) of its own;
+    residuals from a seeded device pool per class; factors cached on the
+    device under an HBM budget; latency = completion (HIP event on the lane's
+    stream) minus arrival. The garbage collector stays on; the objects alive
+    before the stream are frozen out of its generations. The first request of
+    every class is compared with the oracle.
     """
     import torch
 
     from paper_1712_00403_amd import serve, workloads
     mix = {"2d_16_p2": 0.70, "3d_64_p3": 0.25, "3d_96_p4": 0.05}
-    problems = {"2d_16_p2": lambda: workloads.taylor_hood_problem((16, 16), 2, unit_weights=True),
-                "3d_64_p3": lambda: workloads.taylor_hood_problem((64, 64, 64), 3),
-                "3d_96_p4": lambda: workloads.taylor_hood_problem((96, 96, 96), 4)}
-    out = {"rate_per_s": 2000.0, "seconds": args.serve_seconds, "mix": mix, "precisions": {}}
+    shapes = {"2d_16_p2": ((16, 16), 2, True), "3d_64_p3": ((64, 64, 64), 3, False),
+              "3d_96_p4": ((96, 96, 96), 4, False)}
+    problems = {k: (lambda v=v: workloads.taylor_hood_problem(v[0], v[1], unit_weights=v[2]))
+                for k, v in shapes.items()}
+    out = {"rate_per_s": 2000.0, "seconds": args.serve_seconds, "mix": mix, "lanes": "one HIP stream per class",
+           "gc": "enabled; objects alive before the stream frozen (gc.freeze)", "precisions": {}}
+    oracle_cache = {}
     for prec in precisions:
-        classes = {k: serve.RequestClass(k, f, prec) for k, f in problems.items()}
+        classes = {k: serve.RequestClass(k, f, prec, lane) for lane, (k, f) in enumerate(problems.items())}
         arrivals = serve.poisson_arrivals(2000.0, args.serve_seconds, mix, seed=4)
         ex = serve.GpuExecutor(classes, slots=4, seed=4)
         srv = serve.Server(classes, ex, hbm_budget=16 << 30)
@@ -388,26 +524,53 @@ def bench_serve(args, precisions):
             srv.step()
             srv.collect(wait=True)
         torch.cuda.synchronize()
-        # no garbage-collector pauses inside the timed stream (a serving
-        # process collects between bursts)
+        keep = {}
+        for i, (_, c) in enumerate(arrivals):
+            if c not in keep.values():
+                keep[i] = c
         gc.collect()
-        gc.disable()
+        gc.freeze()
         t0 = time.perf_counter()
         ex.t0, ex.ev_ref = t0, None
         try:
-            reqs = serve.run_stream(srv, arrivals, lambda: time.perf_counter() - t0, {k: 4 for k in problems})
+            reqs = serve.run_stream(srv, arrivals, lambda: time.perf_counter() - t0, {k: 4 for k in problems},
+                                    keep=keep)
         finally:
-            gc.enable()
+            gc.unfreeze()
         summ = serve.latency_summary(reqs, args.serve_seconds)
         summ.update({"steps": srv.steps, "plan_cache_bytes": srv.cache.bytes, "evictions": srv.cache.evictions,
                      "offered_dof_per_s": sum(r.dofs for r in reqs) / args.serve_seconds})
-        out["precisions"][prec] = summ
         log(f"serving {prec}: {summ['requests']} requests, p50 {summ['p50_ms']:.3f} ms, "
             f"p99 {summ['p99_ms']:.3f} ms, {summ['dof_per_s'] / 1e9:.2f} GDOF/s, {srv.steps} steps")
-        for pc, _ in srv.cache.entries.values():
-            pc.close()
+        summ["checked_requests"] = served_errors(ex, srv, classes, reqs, keep, shapes, oracle_cache)
+        out["precisions"][prec] = summ
+        for entry, _ in srv.cache.entries.values():
+            entry.close()
         del ex, srv
         torch.cuda.empty_cache()
+    return out
+
+
+def served_errors(ex, srv, classes, reqs, keep, shapes, cache):
+    """Per kept request: largest per-block relative errors (2-norm, element-wise) against the oracle."""
+    from oracle.assemble import pressure_1d, taylor_hood_velocity_1d
+    from oracle.fd import FDFactors, block_apply, velocity_weights
+    out = {}
+    for rid, c in keep.items():
+        n_el, p, unit = shapes[c]
+        slot = reqs[rid].slot
+        entry = srv.cache.entries[c][0]
+        if (c, slot) not in cache:
+            d = len(n_el)
+            Kv, Mv = taylor_hood_velocity_1d(n_el[0], p)
+            facs = [FDFactors([Kv] * d, [Mv] * d, np.ones(d) if unit else velocity_weights(d, k)) for k in range(d)]
+            r = ex.pool_residuals(classes[c], entry.N)[slot]
+            cache[(c, slot)] = block_apply(facs, [pressure_1d(n_el[0], p)] * d, r)
+        zo = cache[(c, slot)]
+        z = ex.kept[rid].double().cpu().numpy()
+        e = block_errors(z[None, :], [zo], entry.pc.offsets)
+        out[c] = {"request": rid, "rel_err_max": e["rel_err_max"], "rel_maxnorm_err_max": e["rel_maxnorm_err_max"]}
+        log(f"  served {c} request {rid}: rel err {e['rel_err_max']:.2e}, rel max err {e['rel_maxnorm_err_max']:.2e}")
     return out
 
 

@@ -40,6 +40,7 @@ struct fd_plan_s {
   const void* scale_dev = nullptr;                      // D^{-1/2}, I/O type
   int MT[3] = {0, 0, 0}, KS[3] = {0, 0, 0};
   int device = 0;
+  int family_cap = 3;  // most capable kernel family the plan's passes may use
 };
 
 struct fd_batch_s {
@@ -183,11 +184,11 @@ fd_status validate_work(const fd_work& wk) {
 }
 
 fd_status run_work(int count, const fd_work* work, hipStream_t stream) {
-  // FD_KERNEL=v1 / v2 caps the kernel family (diagnostics and tests of the
-  // fallbacks); the default picks the most capable family a unit fits.
-  const char* kenv = std::getenv("FD_KERNEL");
-  const int kernel_family = (kenv && std::strcmp(kenv, "v1") == 0) ? 1
-                          : (kenv && std::strcmp(kenv, "v2") == 0) ? 2 : 3;
+  // the most capable kernel family every plan of the call allows (the
+  // default picks the most capable family a unit fits)
+  int kernel_family = 3;
+  for (int i = 0; i < count; ++i)
+    if (work[i].plan) kernel_family = std::min(kernel_family, work[i].plan->family_cap);
   for (int i = 0; i < count; ++i) {
     fd_status s = validate_work(work[i]);
     if (s != FD_OK) return s;
@@ -345,6 +346,46 @@ fd_status run_work(int count, const fd_work* work, hipStream_t stream) {
 
 // ---------------------------------------------------------------- persistent batch
 
+// Descriptor of the pass of `wk` in `stage` with body choice `choice`
+// (kBodyWide, kBodyNarrow, kBodyPipelined; passes without a pipelined body
+// run wide), its body and the LDS bytes it needs; false if the work has no
+// pass in that stage.
+static bool batch_pass(int prec, const fd_work& wk, int stage, int choice, int* body, fdk::BatchDesc* out,
+                       size_t* smem) {
+  fdk::PassDesc u;
+  if (wk.nrhs == 0 || !unit_pass(wk.plan, wk, stage, u)) return false;
+  fdk::BatchDesc bd{};
+  bd.u = u;
+  bd.mode = stage_mode(u);
+  bd.scale = (u.flags & fdk::kPreScale) ? 1 : (u.flags & fdk::kPostScale) ? 2 : 0;
+  int b = choice == fdk::kBodyNarrow ? fdk::kBodyNarrow : fdk::kBodyWide;
+  int chunk = 0, mt3 = 0;
+  size_t sm3 = 0;
+  // the pipelined body loads raw input straight into LDS and stores raw
+  // accumulators: passes that scale either run an LDS-resident body
+  if (choice == fdk::kBodyPipelined && bd.scale == 0 && u.pv1 &&
+      fdk::batch_plan3(prec, bd.mode, u.MT, &mt3, &chunk, &sm3)) {
+    b = fdk::kBodyPipelined;
+    bd.mt = mt3;
+    *smem = sm3;
+  } else {
+    bd.mt = fdk::batch_mt(prec, u.MT);
+    chunk = fdk::batch_chunk(prec, bd.mode, u.MT, b == fdk::kBodyNarrow);
+    *smem = fdk::batch_lds_bytes(prec, u.n, bd.mode == 2);
+  }
+  const int64_t NQ = int64_t(u.A) * u.B;
+  bd.u.tiles_per_rhs = int32_t((NQ + chunk - 1) / chunk);
+  *body = b;
+  *out = bd;
+  return true;
+}
+
+// Order of the passes inside a stage (segments of equal keys): largest
+// row-tile count first, then body, mode and scaling.
+static std::tuple<int, int, int, int> batch_key(int body, const fdk::BatchDesc& bd) {
+  return std::make_tuple(-bd.mt, body, bd.mode, bd.scale);
+}
+
 static fd_status batch_build_layout(fd_batch_s* b, int choice) {
   auto& L = b->lay[choice];
   for (int stage = 0; stage < kStages; ++stage) {
@@ -356,38 +397,18 @@ static fd_status batch_build_layout(fd_batch_s* b, int choice) {
     // passes of this stage, grouped by body (kind, mode, row tiles, scaling)
     std::vector<std::pair<int, fdk::BatchDesc>> passes;  // (body, descriptor)
     for (const fd_work& wk : b->works) {
-      fdk::PassDesc u;
-      if (wk.nrhs == 0 || !unit_pass(wk.plan, wk, stage, u)) continue;
-      fdk::BatchDesc bd{};
-      bd.u = u;
-      bd.mode = stage_mode(u);
-      bd.scale = (u.flags & fdk::kPreScale) ? 1 : (u.flags & fdk::kPostScale) ? 2 : 0;
-      int body = choice == fdk::kBodyNarrow ? fdk::kBodyNarrow : fdk::kBodyWide;
-      int chunk = 0, mt3 = 0;
-      size_t sm3 = 0;
-      // the pipelined body loads raw input straight into LDS and stores raw
-      // accumulators: passes that scale either run an LDS-resident body
-      if (choice == fdk::kBodyPipelined && bd.scale == 0 && u.pv1 &&
-          fdk::batch_plan3(b->prec, bd.mode, u.MT, &mt3, &chunk, &sm3)) {
-        body = fdk::kBodyPipelined;
-        bd.mt = mt3;
-        b->smem = std::max(b->smem, sm3);
-      } else {
-        bd.mt = fdk::batch_mt(b->prec, u.MT);
-        chunk = fdk::batch_chunk(b->prec, bd.mode, u.MT, body == fdk::kBodyNarrow);
-        b->smem = std::max(b->smem, fdk::batch_lds_bytes(b->prec, u.n, bd.mode == 2));
-      }
+      int body = 0;
+      fdk::BatchDesc bd;
+      size_t sm = 0;
+      if (!batch_pass(b->prec, wk, stage, choice, &body, &bd, &sm)) continue;
+      b->smem = std::max(b->smem, sm);
       if (body != fdk::kBodyWide) L.differs[stage] = true;
-      const int64_t NQ = int64_t(u.A) * u.B;
-      bd.u.tiles_per_rhs = int32_t((NQ + chunk - 1) / chunk);
       passes.emplace_back(body, bd);
     }
     // segments of a stage run one after another on every workgroup: the
     // largest row-tile counts first, so that the tiles left when workgroups
     // reach the stage's barrier are the cheapest ones
-    auto key = [](const std::pair<int, fdk::BatchDesc>& x) {
-      return std::make_tuple(-x.second.mt, x.first, x.second.mode, x.second.scale);
-    };
+    auto key = [](const std::pair<int, fdk::BatchDesc>& x) { return batch_key(x.first, x.second); };
     std::stable_sort(passes.begin(), passes.end(), [&](const auto& x, const auto& y) { return key(x) < key(y); });
     int64_t t = 0;
     for (size_t i = 0; i < passes.size(); ++i) {
@@ -476,6 +497,23 @@ static fd_status batch_launch(fd_batch_s* b, hipStream_t stream) {
   hipError_t e = fdk::batch_launch(a, b->prec, int(grid), b->smem, stream);
   if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
   b->arrivals += uint32_t(b->phases) * uint32_t(grid);  // every workgroup passes each barrier once
+  return FD_OK;
+}
+
+// Works a persistent batch accepts: valid works of one precision class with
+// every factor order <= 128, FP8 split excluded.
+static fd_status batch_validate(int32_t count, const fd_work* work, const char* who) {
+  for (int i = 0; i < count; ++i) {
+    fd_status s = validate_work(work[i]);
+    if (s != FD_OK) return s;
+    for (int d = 0; d < work[i].plan->ndim; ++d)
+      if (work[i].plan->n[d] > 16 * fdk::kBatchMaxMT)
+        return fail(FD_E_UNSUPPORTED, std::string(who) + ": factor order above 128 (use fd_apply_batched)");
+    if (work[i].plan->prec != work[0].plan->prec)
+      return fail(FD_E_UNSUPPORTED, std::string(who) + ": plans of different precision classes");
+  }
+  if (count > 0 && work[0].plan->prec == FD_FP8_SPLIT)
+    return fail(FD_E_UNSUPPORTED, std::string(who) + ": no persistent-batch body for FD_FP8_SPLIT");
   return FD_OK;
 }
 
@@ -613,6 +651,12 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
   p->ndim = ndim;
   p->prec = int(prec);
   p->mass_only = (K == nullptr);
+  // FD_KERNEL=v1 / v2 at setup caps the kernel family of the plan's passes
+  // (diagnostics and tests of the fallback kernels)
+  if (const char* kenv = std::getenv("FD_KERNEL")) {
+    if (std::strcmp(kenv, "v1") == 0) p->family_cap = 1;
+    else if (std::strcmp(kenv, "v2") == 0) p->family_cap = 2;
+  }
   p->N = 1;
   for (int i = 0; i < ndim; ++i) {
     if (n[i] < 2 || n[i] > fdk::kMaxN) {
@@ -929,16 +973,9 @@ fd_status fd_apply(fd_plan plan, const void* r, void* z, int32_t nrhs, int64_t l
 fd_status fd_batch_create(int32_t count, const fd_work* work, fd_batch* out) {
   if (!out || count < 1 || !work) return fail(FD_E_ARG, "fd_batch_create: bad arguments");
   *out = nullptr;
-  for (int i = 0; i < count; ++i) {
-    fd_status s = validate_work(work[i]);
+  {
+    fd_status s = batch_validate(count, work, "fd_batch_create");
     if (s != FD_OK) return s;
-    for (int d = 0; d < work[i].plan->ndim; ++d)
-      if (work[i].plan->n[d] > 16 * fdk::kBatchMaxMT)
-        return fail(FD_E_UNSUPPORTED, "fd_batch_create: factor order above 128 (use fd_apply_batched)");
-    if (work[i].plan->prec != work[0].plan->prec)
-      return fail(FD_E_UNSUPPORTED, "fd_batch_create: plans of different precision classes");
-  if (count > 0 && work[0].plan->prec == FD_FP8_SPLIT)
-    return fail(FD_E_UNSUPPORTED, "fd_batch_create: no persistent-batch body for FD_FP8_SPLIT");
   }
   auto* b = new fd_batch_s;
   b->prec = work[0].plan->prec;

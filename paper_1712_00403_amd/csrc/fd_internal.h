@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <vector>
 
@@ -15,6 +16,7 @@ constexpr int kTileP = 16 * kWaves;
 constexpr int kMaxN = 256;        // largest factor order
 constexpr int kMaxMT = kMaxN / 16;
 constexpr int kMaxDesc = 8;       // work units per launch (kernel-argument table)
+constexpr int kMaxDevices = 64;   // per-device launch state
 
 enum PassFlags : int32_t {
   kFuseLambda = 1,   // mode product with F1, divide by Lambda, mode product with F2

@@ -1,15 +1,18 @@
 """GPU parity of the persistent batched apply (one launch for many heterogeneous patches)."""
+import os
+import sys
+import time
+
 import numpy as np
 import pytest
 
 from oracle.assemble import pressure_1d, taylor_hood_velocity_1d
 from oracle.fd import FDFactors, block_apply, velocity_weights
 from paper_1712_00403_amd import workloads
+from parity_util import TOL, TOL_MAX, check_close
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
-
-TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-2, "bf16_split": 1e-4, "f16": 5e-3, "f16_split": 1e-4}
 
 # (n_el, p, geometry or None): 3D and 2D, every pressure degree 1..5, simple and
 # coefficient-aware blocks, factor orders from 3 to 100
@@ -19,10 +22,6 @@ PATCHES = [((5, 7, 4), 2, None), ((9, 4, 6), 3, "sine"), ((3, 5, 8), 4, None), (
 
 def _case(msg):
     print(f"[gpu case] {msg}", flush=True)
-
-
-def _rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
 def _geometry(name, ndim):
@@ -111,8 +110,7 @@ def test_persistent_batch_matches_oracle(prec, config):
         for j in range(nrhs):
             zo = block_apply(facs, Mp, r[j], pres_scale=ps, vel_scales=vs)
             for a, b in zip(pc.offsets[:-1], pc.offsets[1:]):
-                err = _rel(z[j, a:b], zo[a:b])
-                assert err < TOL[prec], f"block [{a},{b}) residual {j}: rel err {err:.3e}"
+                check_close(z[j, a:b], zo[a:b], prec, f"block [{a},{b}) residual {j}")
     batch.close()
     for pc in pcs:
         pc.close()
@@ -141,7 +139,7 @@ def test_persistent_batch_tuning_keeps_results():
         z = zt.cpu().numpy().astype(np.float64)
         zo = block_apply(facs, Mp, r[0], pres_scale=ps, vel_scales=vs)
         for a, b in zip(pc.offsets[:-1], pc.offsets[1:]):
-            assert _rel(z[0, a:b], zo[a:b]) < TOL["f32"]
+            check_close(z[0, a:b], zo[a:b], "f32", f"block [{a},{b})")
     batch.close()
     for pc in pcs:
         pc.close()
@@ -165,3 +163,93 @@ def test_persistent_batch_rejects_large_factors():
             batch.set_config(bad)
     batch.close()
     pc.close()
+
+
+GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+_C4 = {}
+
+
+def _c4_setup():
+    """The 256-patch coefficient-aware batch: descriptors, residuals, the library's host setup (once)."""
+    if not _C4:
+        from concurrent.futures import ThreadPoolExecutor
+        from paper_1712_00403_amd.geometry import geometry_blocks
+        sys.path.insert(0, GOLDEN_DIR)
+        import make_batch_golden as mk
+        patches, sizes, res = mk.batch_inputs()
+        geo = workloads.sine_geometry(3)
+        probs = [workloads.taylor_hood_problem(n_el, p, unit_weights=True) for n_el, p in patches]
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=16) as ex:
+            blocks = list(ex.map(lambda pr: geometry_blocks(pr, geo), probs))
+        print(f"  host setup of {len(probs)} patches: {time.perf_counter() - t0:.1f} s", flush=True)
+        golden = dict(np.load(os.path.join(GOLDEN_DIR, "batch_256_sampled.npz")))
+        _C4.update(mk=mk, patches=patches, sizes=sizes, res=res, geo=geo, probs=probs, blocks=blocks,
+                   golden=golden)
+    return _C4
+
+
+def check_c4_samples(Z, offs, pcs, c4, prec, what):
+    """Compare the sampled pencils of the checked patches with the oracle's values; returns worst errors."""
+    mk, golden = c4["mk"], c4["golden"]
+    worst = (0.0, 0.0)
+    for i in golden["patches"]:
+        n_el, p = c4["patches"][i]
+        zi = Z[offs[i]:offs[i + 1]]
+        po = pcs[i].offsets
+        assert len(po) - 1 == len(mk.patch_blocks(n_el, p))
+        for b in range(len(po) - 1):
+            zb = zi[po[b]:po[b + 1]]
+            idx = golden[f"p{i}_b{b}_idx"]
+            zo = golden[f"p{i}_b{b}_val"]
+            d = zb[idx] - zo
+            assert np.all(np.isfinite(zb[idx])), f"{what} patch {i} block {b}: non-finite entries"
+            e2 = float(np.sqrt(np.mean(d * d)) / golden[f"p{i}_b{b}_rms"])
+            emax = float(np.max(np.abs(d)) / golden[f"p{i}_b{b}_max"])
+            assert e2 < TOL[prec] and emax < TOL_MAX[prec], (
+                f"{what} patch {i} n_el={n_el} p={p} block {b}: sampled rel err {e2:.3e}, rel max err {emax:.3e}")
+            worst = (max(worst[0], e2), max(worst[1], emax))
+    return worst
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLDEN_DIR, "batch_256_sampled.npz")),
+                    reason="stored oracle values not generated (tests/golden/make_batch_golden.py)")
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_c4_batch_256_patches_largest_and_drawn(prec):
+    """The 256-patch batch in one persistent launch (default and tuned configurations, as timed by the bench).
+
+    The 8 largest patches (n up to 96 per direction) and 8 drawn ones are
+    compared with the oracle at whole sampled pencils of every block (corner
+    pencils in the first and last tiles of every pass, two drawn ones), in
+    the RMS and element-wise, each relative to the block's oracle RMS / max.
+    """
+    _case(f"256-patch coefficient-aware batch, prec={prec}")
+    from paper_1712_00403_amd import fd
+    from paper_1712_00403_amd.geometry import GeometryPreconditioner
+    c4 = _c4_setup()
+    pcs = [GeometryPreconditioner(pr, c4["geo"], precision=prec, blocks=b) for pr, b in zip(c4["probs"], c4["blocks"])]
+    assert [pc.N for pc in pcs] == c4["sizes"]
+    dt = torch.float64 if prec == "f64" else torch.float32
+    offs = np.concatenate([[0], np.cumsum(c4["sizes"])]).astype(np.int64)
+    R = torch.from_numpy(np.concatenate(c4["res"])).to(dt).cuda()
+    Z = torch.full_like(R, float("nan"))
+    eb = R.element_size()
+    works = []
+    for i, pc in enumerate(pcs):
+        works += pc.works(R.data_ptr() + int(offs[i]) * eb, Z.data_ptr() + int(offs[i]) * eb, 1)
+    batch = fd.Batch(works)
+    batch.apply()
+    batch.check()
+    torch.cuda.synchronize()
+    e = check_c4_samples(Z.double().cpu().numpy(), offs, pcs, c4, prec, "default config")
+    print(f"  default config {batch.info()['config']}: sampled rel err {e[0]:.3e}, rel max err {e[1]:.3e}")
+    cfg = batch.tune(reps=2)
+    Z.fill_(float("nan"))
+    batch.apply()
+    batch.check()
+    torch.cuda.synchronize()
+    e = check_c4_samples(Z.double().cpu().numpy(), offs, pcs, c4, prec, f"tuned config {cfg}")
+    print(f"  tuned config {cfg}: sampled rel err {e[0]:.3e}, rel max err {e[1]:.3e}")
+    batch.close()
+    for pc in pcs:
+        pc.close()

@@ -1,9 +1,10 @@
 """GPU parity: the HIP FD apply against the FP64 oracle, element by element.
 
-Each case prints its name before touching the GPU. Relative errors are per
-residual and per block (the pressure block's entries are orders of magnitude
-larger than the velocity ones, so one norm over the whole block vector would
-hide velocity errors).
+Each case prints its name before touching the GPU. Errors are per residual
+and per block (the pressure block's entries are orders of magnitude larger
+than the velocity ones, so one norm over the whole block vector would hide
+velocity errors), in the relative 2-norm and element-wise (relative
+max-norm), each against the precision's tolerance.
 """
 import numpy as np
 import pytest
@@ -11,14 +12,10 @@ import pytest
 from oracle.assemble import pressure_1d, taylor_hood_velocity_1d
 from oracle.fd import FDFactors, block_apply, fd_apply, mass_solve_banded, velocity_weights
 from paper_1712_00403_amd import workloads
+from parity_util import TOL, check_blocks, check_close
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
-
-# per-precision tolerance on ||z - z_oracle|| / ||z_oracle||
-# (FP8 split: a rounding emulation of the mode products puts it at 2.5-3e-3)
-TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-2, "bf16_split": 1e-4, "f16": 5e-3, "f16_split": 1e-4,
-       "fp8_split": 1e-2}
 
 
 def _fd():
@@ -33,10 +30,6 @@ def _case(msg):
 def _vel_factors(n_el, p):
     vel = [taylor_hood_velocity_1d(n, p) for n in n_el]
     return [v[0] for v in vel], [v[1] for v in vel]
-
-
-def _rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
 def _run_plan(plan, r, inplace=False, ld=None):
@@ -72,8 +65,7 @@ def test_fd3d_velocity_block(prec, n_el, p, w):
     r = workloads.residuals(11, 3, plan.N)
     z = _run_plan(plan, r)
     for j in range(r.shape[0]):
-        err = _rel(z[j], fd_apply(f, r[j]))
-        assert err < TOL[prec], f"residual {j}: rel err {err:.3e}"
+        check_close(z[j], fd_apply(f, r[j]), prec, f"residual {j}")
     plan.close()
 
 
@@ -89,8 +81,7 @@ def test_fd2d_velocity_block(prec, n_el, p):
     r = workloads.residuals(12, 4, plan.N)
     z = _run_plan(plan, r)
     for j in range(r.shape[0]):
-        err = _rel(z[j], fd_apply(f, r[j]))
-        assert err < TOL[prec], f"residual {j}: rel err {err:.3e}"
+        check_close(z[j], fd_apply(f, r[j]), prec, f"residual {j}")
     plan.close()
 
 
@@ -103,8 +94,7 @@ def test_pressure_mass_block(prec, n_el, p):
     r = workloads.residuals(13, 2, plan.N)
     z = _run_plan(plan, r)
     for j in range(r.shape[0]):
-        err = _rel(z[j], mass_solve_banded(Ms, r[j]))
-        assert err < TOL[prec], f"residual {j}: rel err {err:.3e}"
+        check_close(z[j], mass_solve_banded(Ms, r[j]), prec, f"residual {j}")
     plan.close()
 
 
@@ -118,7 +108,7 @@ def test_inplace_and_strided(prec):
     for inplace in (True, False):
         z = _run_plan(plan, r, inplace=inplace, ld=plan.N + 37)
         for j in range(3):
-            assert _rel(z[j], fd_apply(f, r[j])) < TOL[prec]
+            check_close(z[j], fd_apply(f, r[j]), prec)
     plan.close()
 
 
@@ -141,7 +131,7 @@ def test_scaled_variant(prec):
     s = 1.0 / np.sqrt(D)
     for j in range(2):
         zo = s * fd_apply(f, s * r[j])
-        assert _rel(z[j], zo) < TOL[prec]
+        check_close(z[j], zo, prec)
     plan.close()
 
 
@@ -175,37 +165,54 @@ def test_block_preconditioner_mixed_batch(prec):
         for j in range(2):
             zo = block_apply(facs, Mp, r[j])
             for a, b in zip(pc.offsets[:-1], pc.offsets[1:]):
-                assert _rel(z[j, a:b], zo[a:b]) < TOL[prec]
+                check_close(z[j, a:b], zo[a:b], prec)
         pc.close()
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "fp8_split"])
-def test_full_size_64cube_p3(prec):
-    """The 64^3, p = 3 block (n_V = 129, n_Q = 67) in the launch configuration of the bench."""
-    _case(f"full-size 64^3 p=3 block, prec={prec}")
+_FULL = {}
+
+
+def _full_size_oracle(name, n_el, p, nrhs, seed):
+    """Residuals and oracle block vectors of a full-size TH patch (computed once per module)."""
+    if name not in _FULL:
+        Ks, Ms = _vel_factors(n_el, p)
+        facs = [FDFactors(Ks, Ms, velocity_weights(3, k)) for k in range(3)]
+        Mp = [pressure_1d(n, p) for n in n_el]
+        N = 3 * int(np.prod([K.shape[0] for K in Ks])) + int(np.prod([M.shape[0] for M in Mp]))
+        r = workloads.residuals(seed, nrhs, N)
+        _FULL[name] = (r, [block_apply(facs, Mp, r[j]) for j in range(nrhs)])
+    return _FULL[name]
+
+
+def _full_size_case(name, n_el, p, nrhs, seed, prec, sizes):
     from paper_1712_00403_amd.precond import BlockPreconditioner
-    prob = workloads.CONFIGS["3d_64_p3_16rhs"]["problem"]()
+    prob = workloads.taylor_hood_problem(n_el, p)
     pc = BlockPreconditioner(prob, precision=prec)
-    assert pc.sizes == [129 ** 3] * 3 + [67 ** 3]
-    nrhs = 2
-    r = workloads.residuals(1, nrhs, pc.N)
+    assert pc.sizes == sizes
+    r, zo = _full_size_oracle(name, n_el, p, nrhs, seed)
     dt = torch.float64 if prec == "f64" else torch.float32
     z = pc.apply(torch.from_numpy(r).to(dt).cuda())
     torch.cuda.synchronize()
     z = z.cpu().numpy().astype(np.float64)
-    Ks, Ms = _vel_factors(prob.n_el, 3)
-    Mp = [pressure_1d(n, 3) for n in prob.n_el]
-    for k in range(4):
-        a, b = pc.offsets[k], pc.offsets[k + 1]
-        if k < 3:
-            f = FDFactors(Ks, Ms, velocity_weights(3, k))
-            zo = fd_apply(f, r[0, a:b])
-        else:
-            zo = mass_solve_banded(Mp, r[0, a:b])
-        err = _rel(z[0, a:b], zo)
-        print(f"  block {k}: rel err {err:.3e}")
-        assert err < TOL[prec]
+    for j in range(nrhs):
+        for k, (a, b) in enumerate(zip(pc.offsets[:-1], pc.offsets[1:])):
+            e2, emax = check_close(z[j, a:b], zo[j][a:b], prec, f"residual {j} block {k}")
+            print(f"  residual {j} block {k}: rel err {e2:.3e}, rel max err {emax:.3e}")
     pc.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f16", "bf16_split", "f16_split", "fp8_split"])
+def test_full_size_64cube_p3(prec):
+    """The 64^3, p = 3 patch (n_V = 129, n_Q = 67) in the launch configuration of the bench, every residual."""
+    _case(f"full-size 64^3 p=3 block vector, 2 residuals, prec={prec}")
+    _full_size_case("64_p3", (64, 64, 64), 3, 2, 1, prec, [129 ** 3] * 3 + [67 ** 3])
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_full_size_96cube_p4(prec):
+    """The 96^3, p = 4 patch of the serving mix: n_V = 194 in all three directions (FP64: split last mode)."""
+    _case(f"full-size 96^3 p=4 block vector, prec={prec}")
+    _full_size_case("96_p4", (96, 96, 96), 4, 1, 4, prec, [194 ** 3] * 3 + [100 ** 3])
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "bf16_split"])
@@ -219,7 +226,7 @@ def test_global_fragment_kernels(prec, monkeypatch):
     r = workloads.residuals(16, 2, plan.N)
     z = _run_plan(plan, r)
     for j in range(2):
-        assert _rel(z[j], fd_apply(f, r[j])) < TOL[prec]
+        check_close(z[j], fd_apply(f, r[j]), prec)
     plan.close()
 
 
@@ -234,7 +241,7 @@ def test_large_factor_96_elements_p4(prec, n_el):
     r = workloads.residuals(17, 2, plan.N)
     z = _run_plan(plan, r)
     for j in range(2):
-        assert _rel(z[j], fd_apply(f, r[j])) < TOL[prec]
+        check_close(z[j], fd_apply(f, r[j]), prec)
     plan.close()
 
 
@@ -260,8 +267,7 @@ def test_geometry_variant_block_apply(prec, ndim, n_el, p, geo):
     for j in range(2):
         zo = block_apply(facs, gb.pres_M, r[j], pres_scale=gb.pres_scale, vel_scales=gb.vel_scales)
         for a, b in zip(pc.offsets[:-1], pc.offsets[1:]):
-            err = _rel(z[j, a:b], zo[a:b])
-            assert err < TOL[prec], f"residual {j} block [{a},{b}): rel err {err:.3e}"
+            check_close(z[j, a:b], zo[a:b], prec, f"residual {j} block [{a},{b})")
     pc.close()
 
 
@@ -276,7 +282,7 @@ def test_largest_factor_order_256(prec):
     r = workloads.residuals(18, 2, plan.N)
     z = _run_plan(plan, r)
     for j in range(2):
-        assert _rel(z[j], fd_apply(f, r[j])) < TOL[prec]
+        check_close(z[j], fd_apply(f, r[j]), prec)
     plan.close()
 
 
@@ -289,7 +295,7 @@ def test_smallest_factor_order_2_and_empty_work():
     r = workloads.residuals(19, 3, plan.N)
     z = _run_plan(plan, r)
     for j in range(3):
-        assert _rel(z[j], mass_solve_banded(Ms, r[j])) < TOL["f64"]
+        check_close(z[j], mass_solve_banded(Ms, r[j]), "f64")
     buf = torch.full((1, plan.N), 7.0, dtype=torch.float64, device="cuda")
     plan.apply_ptr(buf.data_ptr(), buf.data_ptr(), 0, plan.N, torch.cuda.current_stream().cuda_stream)
     torch.cuda.synchronize()
@@ -341,7 +347,7 @@ def test_fp64_orders_up_to_224_run_pipelined():
     # the last mode (n = 194) runs as two launches in stage 2
     assert sum(l["count"] for l in launches if l["stage"] == "last_mode_fused") == 2
     for j in range(r.shape[0]):
-        assert _rel(z[j], fd_apply(f, r[j])) < TOL["f64"]
+        check_close(z[j], fd_apply(f, r[j]), "f64")
     plan.close()
 
 
@@ -384,6 +390,5 @@ def test_random_orders(prec, shape):
     r = workloads.residuals(int(rng.integers(0, 1000)), 2, plan.N)
     z = _run_plan(plan, r)
     for j in range(r.shape[0]):
-        err = _rel(z[j], fd_apply(f, r[j]))
-        assert err < TOL[prec], f"residual {j}: rel err {err:.3e}"
+        check_close(z[j], fd_apply(f, r[j]), prec, f"residual {j}")
     plan.close()

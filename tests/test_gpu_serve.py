@@ -7,6 +7,7 @@ import pytest
 from oracle.assemble import pressure_1d, taylor_hood_velocity_1d
 from oracle.fd import FDFactors, block_apply, velocity_weights
 from paper_1712_00403_amd import workloads
+from parity_util import check_blocks
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -46,15 +47,13 @@ def test_request_alone_equals_request_in_mix(prec):
     in_mix = h_mix[1][2].cpu().numpy()
     assert np.array_equal(alone, in_mix)
     # and against the oracle
-    r = ex.pools["3d_a"][1].double().cpu().numpy()
+    r = srv.cache.entries["3d_a"][0].pool[1].double().cpu().numpy()
     n_el, p = (10, 12, 8), 3
     vel = [taylor_hood_velocity_1d(n, p) for n in n_el]
     facs = [FDFactors([v[0] for v in vel], [v[1] for v in vel], velocity_weights(3, k)) for k in range(3)]
     zo = block_apply(facs, [pressure_1d(n, p) for n in n_el], r)
-    pc = srv.cache.entries["3d_a"][0]
-    tol = 1e-12 if prec == "f64" else 2e-2
-    for a, b in zip(pc.offsets[:-1], pc.offsets[1:]):
-        assert np.linalg.norm(alone[a:b] - zo[a:b]) / np.linalg.norm(zo[a:b]) < tol
+    pc = srv.cache.entries["3d_a"][0].pc
+    check_blocks(alone, zo, pc.offsets, prec, "3d_a slot 1")
 
 
 def test_poisson_stream_completes():
@@ -71,3 +70,92 @@ def test_poisson_stream_completes():
     print(f"  {s['requests']} requests, p50 {s['p50_ms']:.3f} ms, p99 {s['p99_ms']:.3f} ms, steps {srv.steps}")
     assert s["p50_ms"] > 0 and s["p99_ms"] >= s["p50_ms"]
     assert srv.steps <= len(arrivals)
+
+
+_ORACLE = {}
+
+
+def _oracle_z(n_el, p, r, unit_weights, key):
+    """Oracle block vector of a TH patch for residual r (cached by key)."""
+    if key not in _ORACLE:
+        d = len(n_el)
+        vel = [taylor_hood_velocity_1d(n, p) for n in n_el]
+        w = [np.ones(d) if unit_weights else velocity_weights(d, k) for k in range(d)]
+        facs = [FDFactors([v[0] for v in vel], [v[1] for v in vel], w[k]) for k in range(d)]
+        _ORACLE[key] = block_apply(facs, [pressure_1d(n, p) for n in n_el], r)
+    return _ORACLE[key]
+
+
+SERVE_MIX = {"2d_16_p2": ((16, 16), 2, True, 0), "3d_64_p3": ((64, 64, 64), 3, False, 1),
+             "3d_96_p4": ((96, 96, 96), 4, False, 2)}
+
+
+@pytest.mark.parametrize("prec", ["f64", "bf16"])
+def test_served_results_match_oracle(prec):
+    """A Poisson stream over the serving mix (2D 16^2, 64^3 p=3, 96^3 p=4 in lanes of their own).
+
+    The first two served requests of every class are kept and compared with
+    the oracle, block by block, in the 2-norm and element-wise.
+    """
+    _case(f"serving: served results of the three-class mix against the oracle, prec={prec}")
+    from paper_1712_00403_amd import serve
+    classes = {k: serve.RequestClass(k, (lambda v=v: workloads.taylor_hood_problem(v[0], v[1], unit_weights=v[2])),
+                                     prec, v[3]) for k, v in SERVE_MIX.items()}
+    t0 = time.perf_counter()
+    ex = serve.GpuExecutor(classes, slots=2, seed=4, t0=t0)
+    srv = serve.Server(classes, ex, hbm_budget=8 << 30)
+    arrivals = serve.poisson_arrivals(300.0, 0.4, {"2d_16_p2": 0.6, "3d_64_p3": 0.3, "3d_96_p4": 0.1}, seed=5)
+    keep = {}
+    for i, (_, c) in enumerate(arrivals):
+        if sum(1 for v in keep.values() if v == c) < 2:
+            keep[i] = c
+    assert set(keep.values()) == set(SERVE_MIX)
+    reqs = serve.run_stream(srv, arrivals, lambda: time.perf_counter() - t0, {k: 2 for k in classes}, keep=keep)
+    assert all(r.done is not None for r in reqs)
+    s = serve.latency_summary(reqs, 0.4)
+    print(f"  {s['requests']} requests, p50 {s['p50_ms']:.3f} ms, p99 {s['p99_ms']:.3f} ms, steps {srv.steps}")
+    for rid, c in keep.items():
+        n_el, p, unit, _ = SERVE_MIX[c]
+        slot = reqs[rid].slot
+        entry = srv.cache.entries[c][0]
+        r = ex.pool_residuals(classes[c], entry.N)[slot]
+        zo = _oracle_z(n_el, p, r, unit, (c, slot))
+        z = ex.kept[rid].double().cpu().numpy()
+        e2, emax = check_blocks(z, zo, entry.pc.offsets, prec, f"request {rid} ({c}, slot {slot})")
+        print(f"  request {rid} {c}: rel err {e2:.3e}, rel max err {emax:.3e}")
+
+
+def test_hbm_budget_forces_waits_and_evictions():
+    """A budget that holds one 3D class and one result at a time: classes alternate through evictions and waits."""
+    _case("serving: admission under a budget of one class, prec=f32")
+    from paper_1712_00403_amd import serve
+    shapes = {"3d_a": ((10, 12, 8), 3), "3d_c": ((12, 10, 8), 3)}
+    classes = {k: serve.RequestClass(k, (lambda v=v: workloads.taylor_hood_problem(v[0], v[1])), "f32")
+               for k, v in shapes.items()}
+    t0 = time.perf_counter()
+    ex = serve.GpuExecutor(classes, slots=2, seed=4, t0=t0)
+    sizes = {}
+    for k in classes:
+        entry, nbytes = ex.build(classes[k])
+        sizes[k] = (nbytes, ex.io_bytes(entry))
+        entry.close()
+    budget = max(b + io for b, io in sizes.values()) + 1024
+    assert budget < sum(b for b, _ in sizes.values()), sizes
+    srv = serve.Server(classes, ex, hbm_budget=budget)
+    arrivals = [(0.0005 * i, "3d_a" if (i // 2) % 2 == 0 else "3d_c") for i in range(24)]
+    keep = {i: c for i, (_, c) in enumerate(arrivals) if i < 4}
+    reqs = serve.run_stream(srv, arrivals, lambda: time.perf_counter() - t0, {k: 2 for k in classes}, keep=keep)
+    assert all(r.done is not None for r in reqs)
+    print(f"  steps {srv.steps}, evictions {srv.cache.evictions}, waits {srv.waits}, builds {srv.cache.builds}")
+    assert srv.cache.evictions >= 2
+    assert srv.cache.bytes <= budget
+    for rid, c in keep.items():
+        n_el, p = shapes[c]
+        slot = reqs[rid].slot
+        N = ex.kept[rid].numel()
+        r = ex.pool_residuals(classes[c], N)[slot]
+        zo = _oracle_z(n_el, p, r, False, ("budget", c, slot))
+        z = ex.kept[rid].double().cpu().numpy()
+        vel = int(np.prod([2 * n + p - 2 for n in n_el]))
+        offs = [0, vel, 2 * vel, 3 * vel, N]
+        check_blocks(z, zo, offs, "f32", f"request {rid} ({c})")
