@@ -270,6 +270,32 @@ fd_status fd_batch_info(fd_batch batch, int64_t* tiles, int32_t* grid, int32_t* 
 fd_status fd_batch_check(fd_batch batch);
 fd_status fd_batch_destroy(fd_batch batch);
 
+/* The persistent batched apply without any allocation, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): runs `count` works (the same
+ * rules as fd_batch_create: one precision class, every n <= 128, no
+ * FD_FP8_SPLIT) as ONE persistent launch with the body choices of the
+ * configuration word `config` (as fd_batch_set_config; 0 = every stage wide),
+ * computing the same results as an fd_batch with that configuration.
+ * Per call it enqueues on `stream` a one-wavefront fill kernel that zeroes the
+ * barrier counter and the status word, an asynchronous host-to-device copy of
+ * the pass tables, and the batch kernel; it calls no hipMalloc, hipFree or
+ * other allocating routine. The barrier counter, error flag and pass tables
+ * live in a static device array of 2 MiB per GPU (allocated with the code
+ * object, held until the process ends; set up on the first call on a device,
+ * with that device current). Lists whose pass tables exceed it (about 9,000
+ * passes, e.g. more than 400 3D patches of 4 blocks) are FD_E_ARG with a
+ * message. Every call on one GPU shares that array: calls on different
+ * streams that overlap on the device race and give undefined results; calls
+ * ordered on one stream are safe. The host part is serialized internally.
+ * `status`: NULL or a caller-owned device int32 set to 0 by this call and to
+ * 1 if a grid-barrier wait gave up (the grid could not be fully resident;
+ * the results are then undefined); read it after synchronizing. Errors:
+ * FD_E_ARG (as fd_batch_create, a bad configuration word, tables above the
+ * limit), FD_E_UNSUPPORTED (as fd_batch_create), FD_E_HIP. */
+fd_status fd_apply_persistent_static(int32_t count, const fd_work* work, int32_t config, int32_t* status,
+                                     void* stream);
+
 /* ---------------------------------------------------------------- diagnostics */
 
 /* Per-stage kernel timing. While enabled, the launches of each stage of

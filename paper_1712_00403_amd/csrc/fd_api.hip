@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -522,6 +523,60 @@ static int batch_config(const fd_batch_s* b) {
   int c = 0;
   for (int st = 0; st < kStages; ++st) c |= b->width[st] << (2 * st);
   return c;
+}
+
+// ---------------------------------------------------------------- allocation-free persistent apply
+//
+// fd_apply_persistent_static runs a list of works as one persistent launch,
+// like fd_batch_apply, without allocating: the barrier counter, the error
+// flag and the pass tables live in the file-scope device array `scratch`
+// (one copy per GPU, kStaticBytes, held until the process ends). Host code
+// never passes `scratch` itself: the per-device address from
+// hipGetSymbolAddress is kept in g_static[device].ptr and used everywhere.
+
+constexpr size_t kStaticBytes = size_t(2) << 20;  // tables + control words per device
+constexpr size_t kStaticCtl = 256;                // barrier counter at 0, error flag at 128
+constexpr int kStaticMaxDesc = int((kStaticBytes - kStaticCtl) / sizeof(fdk::BatchDesc));
+constexpr int kStaticMaxDevices = 64;
+
+struct StaticDevice {
+  unsigned char* ptr = nullptr;  // device address of `scratch` on this device
+  int cus = 0;
+};
+StaticDevice g_static[kStaticMaxDevices];
+std::mutex g_static_mu;  // the host staging below is shared by all callers
+
+// host staging of one call: passes of a stage before ordering, their order,
+// then the uploaded image (descriptors followed by segments)
+fdk::BatchDesc g_cand[kStaticMaxDesc];
+int g_cand_body[kStaticMaxDesc];
+int g_ord[kStaticMaxDesc];
+fdk::BatchSeg g_seg[kStaticMaxDesc];
+alignas(256) unsigned char g_image[kStaticBytes - kStaticCtl];
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+namespace {
+
+// Per-device set-up (with that device current): the address of this
+// device's copy of `scratch`, and its CU count.
+fd_status static_device(int dev, StaticDevice** out) {
+  if (dev < 0 || dev >= kStaticMaxDevices) return fail(FD_E_UNSUPPORTED, "fd_apply_persistent_static: device index");
+  StaticDevice& sd = g_static[dev];
+  if (!sd.ptr) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    int cus = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+    sd.cus = cus;
+    sd.ptr = static_cast<unsigned char*>(p);
+  }
+  *out = &sd;
+  return FD_OK;
 }
 
 }  // namespace
@@ -1118,6 +1173,105 @@ fd_status fd_batch_destroy(fd_batch b) {
 fd_status fd_apply_batched(int32_t count, const fd_work* work, void* stream) {
   if (count < 0 || (count > 0 && !work)) return fail(FD_E_ARG, "fd_apply_batched: bad count/work");
   return run_work(count, work, static_cast<hipStream_t>(stream));
+}
+
+fd_status fd_apply_persistent_static(int32_t count, const fd_work* work, int32_t config, int32_t* status,
+                                     void* stream) {
+  if (count < 0 || (count > 0 && !work)) return fail(FD_E_ARG, "fd_apply_persistent_static: bad arguments");
+  if (config < 0 || config >= (1 << (2 * kStages)))
+    return fail(FD_E_ARG, "fd_apply_persistent_static: configuration word out of range");
+  for (int st = 0; st < kStages; ++st)
+    if (((config >> (2 * st)) & 3) == 3) return fail(FD_E_ARG, "fd_apply_persistent_static: body choice 3");
+  fd_status s = batch_validate(count, work, "fd_apply_persistent_static");
+  if (s != FD_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  StaticDevice* sd = nullptr;
+  s = static_device(dev, &sd);
+  if (s != FD_OK) return s;
+  const int prec = count > 0 ? work[0].plan->prec : FD_F64;
+  // the pass tables of every stage, in the layout fd_batch_create builds
+  fdk::BatchArgs a{};
+  int nd = 0, ns = 0, last_stage = -1;
+  int64_t max_tiles = 0;
+  size_t smem = 0;
+  for (int stage = 0; stage < kStages; ++stage) {
+    const int choice = (config >> (2 * stage)) & 3;
+    int nc = 0;
+    for (int i = 0; i < count; ++i) {
+      if (nd + nc == kStaticMaxDesc)
+        return fail(FD_E_ARG, "fd_apply_persistent_static: more passes than the " +
+                                  std::to_string(kStaticMaxDesc) + " descriptors of the 2 MiB static table");
+      size_t sm = 0;
+      if (!batch_pass(prec, work[i], stage, choice, &g_cand_body[nc], &g_cand[nc], &sm)) continue;
+      smem = std::max(smem, sm);
+      g_ord[nc] = nc;
+      ++nc;
+    }
+    // stable order of the keys (ties keep the work order)
+    std::sort(g_ord, g_ord + nc, [](int x, int y) {
+      const auto kx = batch_key(g_cand_body[x], g_cand[x]), ky = batch_key(g_cand_body[y], g_cand[y]);
+      return kx < ky || (kx == ky && x < y);
+    });
+    a.stage_seg[stage] = ns;
+    auto* desc = reinterpret_cast<fdk::BatchDesc*>(g_image);
+    int64_t t = 0;
+    for (int k = 0; k < nc; ++k) {
+      const int c = g_ord[k];
+      fdk::BatchDesc bd = g_cand[c];
+      if (k == 0 || batch_key(g_cand_body[g_ord[k - 1]], g_cand[g_ord[k - 1]]) != batch_key(g_cand_body[c], bd)) {
+        fdk::BatchSeg sg{};
+        sg.d0 = nd;
+        sg.t0 = int(t);
+        sg.mode = bd.mode;
+        sg.mt = bd.mt;
+        sg.scale = bd.scale;
+        sg.body = g_cand_body[c];
+        g_seg[ns++] = sg;
+      }
+      bd.u.tile_begin = t;
+      t += int64_t(bd.u.tiles_per_rhs) * bd.u.nrhs;
+      if (t > 0x7fffffffLL) return fail(FD_E_ARG, "fd_apply_persistent_static: too many tiles in one stage");
+      desc[nd++] = bd;
+      g_seg[ns - 1].d1 = nd;
+      g_seg[ns - 1].t1 = int(t);
+    }
+    if (t > 0) last_stage = stage;
+    max_tiles = std::max(max_tiles, t);
+  }
+  a.stage_seg[kStages] = ns;
+  const size_t db = size_t(nd) * sizeof(fdk::BatchDesc), sb = size_t(ns) * sizeof(fdk::BatchSeg);
+  if (kStaticCtl + db + sb > kStaticBytes)
+    return fail(FD_E_ARG, "fd_apply_persistent_static: pass tables of " + std::to_string(db + sb) +
+                              " bytes exceed the 2 MiB static table");
+  if (smem > 160 * 1024) return fail(FD_E_UNSUPPORTED, "fd_apply_persistent_static: factor image exceeds LDS");
+  std::memcpy(g_image + db, g_seg, sb);
+  uint32_t* bar = reinterpret_cast<uint32_t*>(sd->ptr);
+  int32_t* err = status ? status : reinterpret_cast<int32_t*>(sd->ptr + 128);
+  // the counter and the flag start at zero (a fill kernel, no memset node)
+  e = fdk::batch_reset(bar, err, st);
+  if (e != hipSuccess) return hip_fail(e, "batch reset");
+  if (max_tiles == 0) return FD_OK;
+  int per_cu = 0;
+  e = fdk::batch_resident(prec, smem, &per_cu);
+  if (e != hipSuccess) return hip_fail(e, "batch occupancy");
+  if (per_cu < 1) return fail(FD_E_UNSUPPORTED, "fd_apply_persistent_static: batch kernel does not fit a CU");
+  // pageable source: the runtime has consumed g_image when the call returns
+  e = hipMemcpyAsync(sd->ptr + kStaticCtl, g_image, db + sb, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (pass tables)");
+  a.desc = reinterpret_cast<const fdk::BatchDesc*>(sd->ptr + kStaticCtl);
+  a.seg = reinterpret_cast<const fdk::BatchSeg*>(sd->ptr + kStaticCtl + db);
+  a.barrier = bar;
+  a.error = err;
+  a.base = 0;
+  a.last_stage = last_stage;
+  const int64_t grid = std::min<int64_t>(sd->cus, max_tiles);
+  e = fdk::batch_launch(a, prec, int(grid), smem, st);
+  if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
+  return FD_OK;
 }
 
 }  // extern "C"

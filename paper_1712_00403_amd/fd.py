@@ -24,7 +24,7 @@ EXPORTS = ("fd_assemble_1d", "fd_quadrature_1d", "fd_factor_1d", "fd_geometry_co
            "fd_separable_factors", "fd_operator_diagonal", "fd_setup", "fd_destroy",
            "fd_plan_size", "fd_plan_device_bytes", "fd_workspace_bytes", "fd_plan_factors", "fd_apply",
            "fd_apply_batched", "fd_batch_create", "fd_batch_apply", "fd_batch_tune", "fd_batch_set_config",
-           "fd_batch_info", "fd_batch_check", "fd_batch_destroy", "fd_timing_enable", "fd_timing_read", "fd_timing_launches", "fd_last_error")
+           "fd_batch_info", "fd_batch_check", "fd_batch_destroy", "fd_apply_persistent_static", "fd_timing_enable", "fd_timing_read", "fd_timing_launches", "fd_last_error")
 
 
 class FDError(RuntimeError):
@@ -87,8 +87,10 @@ def lib():
     L.fd_batch_set_config.restype = ctypes.c_int
     L.fd_batch_check.argtypes = [ctypes.c_void_p]
     L.fd_batch_destroy.argtypes = [ctypes.c_void_p]
+    L.fd_apply_persistent_static.argtypes = [ctypes.c_int32, ctypes.POINTER(FDWork), ctypes.c_int32,
+                                             ctypes.c_void_p, ctypes.c_void_p]
     for name in ("fd_batch_create", "fd_batch_apply", "fd_batch_tune", "fd_batch_info", "fd_batch_check",
-                 "fd_batch_destroy"):
+                 "fd_batch_destroy", "fd_apply_persistent_static"):
         getattr(L, name).restype = ctypes.c_int
     L.fd_timing_enable.argtypes = [ctypes.c_int32]
     L.fd_timing_read.argtypes = [c_dp, ctypes.POINTER(ctypes.c_int32)]
@@ -394,6 +396,16 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def apply_persistent_static(works, config=0, status=None, stream=None):
+    """works: iterable of (plan, r_ptr, z_ptr, nrhs, ld) -> one allocation-free persistent launch.
+
+    ``status``: None or the device address of an int32 the library sets to 0,
+    or to 1 if a grid barrier gave up (fd_apply_persistent_static).
+    """
+    arr = _work_array(works)
+    _check(lib().fd_apply_persistent_static(len(arr), arr, int(config), status, _stream_handle(stream)))
 
 
 STAGE_NAMES = ("mode1_fwd", "mode2_fwd", "last_mode_fused", "mode2_bwd", "mode1_bwd")
