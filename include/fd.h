@@ -107,6 +107,20 @@ fd_status fd_assemble_1d(int32_t n_el, int32_t degree, int32_t regularity, int32
                          int32_t npts, const double* tau_q, const double* mu_q,
                          int32_t* n_out, double* K, double* M);
 
+/* The Nitsche-modified stiffness factor K~ of the Raviart-Thomas velocity
+ * blocks (Sec. 5, the factors below eq. prec3D_RT), over all m B-splines of
+ * the degree/regularity space on the uniform mesh (no function dropped):
+ *   [K~]_ls = int b'_l b'_s - ( b'_l(1) b_s(1) - b'_l(0) b_s(0)
+ *             + b'_s(1) b_l(1) - b'_s(0) b_l(0) )
+ *             + 2 (c_pen / h) ( b_l(1) b_s(1) + b_l(0) b_s(0) ),   h = 1 / n_el,
+ * the one-direction face terms of the parametric Nitsche form. The matching
+ * mass factor is fd_assemble_1d's M with dirichlet = 0; the experiments use
+ * c_pen = 5 (regularity + 1). *n_out receives m; K (host, m*m column-major,
+ * caller-allocated) may be NULL to query m only. Errors: FD_E_ARG as
+ * fd_assemble_1d, or c_pen < 0. */
+fd_status fd_nitsche_stiffness_1d(int32_t n_el, int32_t degree, int32_t regularity, double c_pen, int32_t* n_out,
+                                  double* K);
+
 /* Gauss-Legendre points and weights on the element mesh used by
  * fd_assemble_1d: x, w host arrays of n_el*npts (element-major). */
 fd_status fd_quadrature_1d(int32_t n_el, int32_t npts, double* x, double* w);
@@ -196,6 +210,21 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K,
 /* Release the plan and its device memory. The caller must make sure no apply
  * using it is still executing. NULL is accepted. */
 fd_status fd_destroy(fd_plan plan);
+
+/* A mass-only plan (P_Q = M_d (x) .. (x) M_1, eq. precQ) applied by the
+ * banded route of Sec. 5.2: each M_i (host FP64, n[i]*n[i] column-major,
+ * symmetric positive definite, bandwidth b_i <= 16, e.g. b_i = degree for
+ * B-spline mass matrices) is factored M_i = L_i L_i^T on the host in FP64,
+ * and an apply runs one launch per direction that solves L_i L_i^T along
+ * that mode for every pencil (O(b_i n_i) per pencil instead of the FD
+ * form's O(n_i^2)); arithmetic in FP64 for FD_F64 plans, FP32 otherwise
+ * (vectors as for fd_setup). The plan works with fd_apply and
+ * fd_apply_batched (alone or beside FD plans of the same I/O type); the
+ * persistent batch and fd_plan_factors refuse it (FD_E_UNSUPPORTED).
+ * Errors: FD_E_ARG (sizes as fd_setup, asymmetry, bandwidth above 16),
+ * FD_E_NOTSPD, FD_E_NOMEM, FD_E_HIP. */
+fd_status fd_setup_mass_banded(int32_t ndim, const int32_t* n, const double* const* M, fd_precision prec,
+                               fd_plan* out);
 
 /* Plan queries: N = prod(n); device bytes held by the plan. */
 int64_t fd_plan_size(fd_plan plan);

@@ -84,3 +84,86 @@ def coefficient_operator(tables, weights, coef, order):
         for b in range(d):
             A = A + (grads[a] * (W * coef[a, b])[None, :]) @ grads[b].T
     return A
+
+
+def rt_velocity_block_variational(n_el, p, k, c_pen):
+    """P_V,k^RT from its variational definition on the parametric cube (eq. precVrt), tiny grids only.
+
+    [P]_ij = a^(e_k B_i, e_k B_j) + sigma^(e_k B_i, e_k B_j) with
+    a^(w, v) = int 2 grad^s w : grad^s v over the cube and
+    sigma^(w, v) = int over the boundary of 2 [ (c_pen / h) w.v
+                   - ((grad^s w) n).v - ((grad^s v) n).w ]
+    (Sec. 5, the parametric forms above eq. precVth), over the basis of the
+    component k of V_h,0^RT (eq. basisRT_V1): degree p+1, regularity p in
+    direction k with its first and last function dropped, degree p,
+    regularity p-1 in the other directions (i_1 fastest). Every symmetric
+    gradient is formed as a d x d matrix at each Gauss point of the cube and
+    of each face (outer normal n = -e_j at eta_j = 0, +e_j at eta_j = 1;
+    h = 1/n_el[j] on the faces normal to e_j). Independent of the
+    Kronecker-sum factorisation of eq. prec3D_RT, which it checks.
+    """
+    from .bspline import basis_derivatives, basis_values, element_quadrature, open_uniform_knots
+
+    d = len(n_el)
+    npts = p + 2
+    tabs = []   # per direction: (knots, degree, keep slice, quadrature points, weights)
+    for j in range(d):
+        deg, reg = (p + 1, p) if j == k else (p, p - 1)
+        knots = open_uniform_knots(n_el[j], deg, reg)
+        xq, wq = element_quadrature(n_el[j], npts)
+        tabs.append((knots, deg, j == k, xq.ravel(), wq.ravel()))
+
+    def values(j, x):
+        knots, deg, drop, _, _ = tabs[j]
+        B = basis_values(knots, deg, x)
+        dB = basis_derivatives(knots, deg, x)
+        return (B[1:-1], dB[1:-1]) if drop else (B, dB)
+
+    def field(pts):
+        """Values (nfun, npt) and gradients (nfun, npt, d) of all B_i at the points (each a list per direction)."""
+        vals = [values(j, pts[j]) for j in range(d)]
+        # multi-indices i_1 fastest, points q_1 fastest: Kronecker products in reversed direction order
+        def kron_rows(mats):
+            out = np.ones((1, 1))
+            for j in range(d):
+                out = np.kron(mats[j], out)
+            return out
+        V = kron_rows([vals[j][0] for j in range(d)])
+        G = np.stack([kron_rows([vals[j][1] if j == a else vals[j][0] for j in range(d)]) for a in range(d)], axis=2)
+        return V, G
+
+    def sym_grad(G):
+        """grad^s of w = e_k B_i for every function and point: (nfun, npt, d, d)."""
+        S = np.zeros(G.shape[:2] + (d, d))
+        S[:, :, k, :] += 0.5 * G     # row k of grad w is grad B_i
+        S[:, :, :, k] += 0.5 * G
+        return S
+
+    def weights_of(ws):
+        W = np.ones(1)
+        for w in ws:
+            W = np.kron(w, W)
+        return W
+
+    # volume term
+    V, G = field([tabs[j][3] for j in range(d)])
+    W = weights_of([tabs[j][4] for j in range(d)])
+    S = sym_grad(G)
+    P = 2.0 * np.einsum("iqab,jqab,q->ij", S, S, W)
+    # face terms
+    for j in range(d):
+        h = 1.0 / n_el[j]
+        for side in (0.0, 1.0):
+            pts = [tabs[t][3] if t != j else np.array([side]) for t in range(d)]
+            ws = [tabs[t][4] if t != j else np.ones(1) for t in range(d)]
+            Vf, Gf = field(pts)
+            Wf = weights_of(ws)
+            Sf = sym_grad(Gf)
+            n = np.zeros(d)
+            n[j] = 1.0 if side == 1.0 else -1.0
+            # w.v = B_i B_j (both along e_k); ((grad^s w) n).v = B_j [ (grad^s w) n ]_k
+            Sn = np.einsum("iqab,b->iqa", Sf, n)[:, :, k]      # [(grad^s w_i) n]_k
+            pen = (2.0 * c_pen / h) * np.einsum("iq,jq,q->ij", Vf, Vf, Wf)
+            cons = 2.0 * (np.einsum("iq,jq,q->ij", Sn, Vf, Wf) + np.einsum("jq,iq,q->ij", Sn, Vf, Wf))
+            P += pen - cons
+    return P

@@ -42,6 +42,11 @@ struct fd_plan_s {
   int MT[3] = {0, 0, 0}, KS[3] = {0, 0, 0};
   int device = 0;
   int family_cap = 3;  // most capable kernel family the plan's passes may use
+  // banded route of a mass-only block (fd_setup_mass_banded): per direction
+  // the band of the Cholesky factor of M_i on the device
+  bool banded = false;
+  int bw[3] = {0, 0, 0};
+  const void* bfac[3] = {nullptr, nullptr, nullptr};
 };
 
 struct fd_batch_s {
@@ -108,6 +113,7 @@ constexpr int kStages = 5;
 
 bool unit_pass(const fd_plan_s* p, const fd_work& wk, int stage, fdk::PassDesc& u) {
   std::memset(&u, 0, sizeof(u));
+  if (p->banded) return false;  // runs the banded solves instead (band_pass)
   const int n1 = p->n[0], n2 = p->n[1], n3 = p->n[2];
   u.in = wk.z;
   u.out = wk.z;
@@ -169,6 +175,28 @@ int stage_mode(const fdk::PassDesc& u) {
   return u.A == 1 ? 0 : 1;
 }
 
+// Mode `stage` of the banded route (stages 0..ndim-1: mode 1 reads r and
+// writes z, the later modes run in place on z).
+bool band_pass(const fd_plan_s* p, const fd_work& wk, int stage, fdk::BandArgs& a) {
+  if (!p->banded || stage >= p->ndim || wk.nrhs == 0) return false;
+  std::memset(&a, 0, sizeof(a));
+  fdk::BandDesc& u = a.u;
+  int A = 1, B = 1;
+  for (int i = 0; i < stage; ++i) A *= p->n[i];
+  for (int i = stage + 1; i < p->ndim; ++i) B *= p->n[i];
+  u.in = stage == 0 ? wk.r : wk.z;
+  u.out = wk.z;
+  u.fac = p->bfac[stage];
+  u.ld = wk.ld;
+  u.A = A;
+  u.n = p->n[stage];
+  u.B = B;
+  u.nrhs = wk.nrhs;
+  u.bw = p->bw[stage];
+  u.tiles_per_rhs = fdk::band_tiles_per_rhs(int64_t(A) * B);
+  return true;
+}
+
 fd_status validate_work(const fd_work& wk) {
   if (!wk.plan) return fail(FD_E_ARG, "fd_apply: NULL plan");
   if (wk.nrhs < 0) return fail(FD_E_ARG, "fd_apply: nrhs < 0");
@@ -204,7 +232,10 @@ fd_status run_work(int count, const fd_work* work, hipStream_t stream) {
       bool any = false;
       for (int i = 0; i < count; ++i) {
         fdk::PassDesc probe;
-        if (work[i].nrhs > 0 && unit_pass(work[i].plan, work[i], stage, probe)) any = true;
+        fdk::BandArgs bprobe;
+        if (work[i].nrhs > 0 && (unit_pass(work[i].plan, work[i], stage, probe) ||
+                                 band_pass(work[i].plan, work[i], stage, bprobe)))
+          any = true;
       }
       if (any) {
         hipError_t e = hipEventCreate(&rec.start);
@@ -334,6 +365,27 @@ fd_status run_work(int count, const fd_work* work, hipStream_t stream) {
         fd_status s = run_units(split_fwd, 3);
         if (s == FD_OK) s = run_units(split_bwd, 1);
         if (s != FD_OK) return s;
+      }
+    }
+    // banded route of mass-only blocks: one launch per work and mode
+    for (int i = 0; i < count; ++i) {
+      fdk::BandArgs ba;
+      if (!band_pass(work[i].plan, work[i], stage, ba)) continue;
+      LaunchRecord lr{stage, 4, ba.u.n, work[i].plan->prec, nullptr, nullptr};
+      if (g_timing) {
+        hipError_t e = hipEventCreate(&lr.start);
+        if (e == hipSuccess) e = hipEventCreate(&lr.end);
+        if (e == hipSuccess) e = hipEventRecord(lr.start, stream);
+        if (e != hipSuccess) return hip_fail(e, "timing event");
+      }
+      if (int64_t(ba.u.tiles_per_rhs) * ba.u.nrhs > 0x7fffffffLL)
+        return fail(FD_E_ARG, "fd_apply: too many tiles in one call");
+      hipError_t e = fdk::launch_band(ba, io_is_f64(work[i].plan->prec), stream);
+      if (e != hipSuccess) return hip_fail(e, "banded kernel launch");
+      if (g_timing) {
+        e = hipEventRecord(lr.end, stream);
+        if (e != hipSuccess) return hip_fail(e, "timing event");
+        g_launch_records.push_back(lr);
       }
     }
     if (rec.start) {
@@ -512,6 +564,8 @@ static fd_status batch_validate(int32_t count, const fd_work* work, const char* 
         return fail(FD_E_UNSUPPORTED, std::string(who) + ": factor order above 128 (use fd_apply_batched)");
     if (work[i].plan->prec != work[0].plan->prec)
       return fail(FD_E_UNSUPPORTED, std::string(who) + ": plans of different precision classes");
+    if (work[i].plan->banded)
+      return fail(FD_E_UNSUPPORTED, std::string(who) + ": banded mass plans run through fd_apply_batched only");
   }
   if (count > 0 && work[0].plan->prec == FD_FP8_SPLIT)
     return fail(FD_E_UNSUPPORTED, std::string(who) + ": no persistent-batch body for FD_FP8_SPLIT");
@@ -644,6 +698,16 @@ fd_status fd_assemble_1d(int32_t n_el, int32_t degree, int32_t regularity, int32
   int m = 0;
   if (fdh::assemble_1d(n_el, degree, regularity, dirichlet, npts, tau_q, mu_q, &m, K, M) != 0)
     return fail(FD_E_ARG, "fd_assemble_1d: invalid n_el/degree/regularity/npts");
+  *n_out = m;
+  return FD_OK;
+}
+
+fd_status fd_nitsche_stiffness_1d(int32_t n_el, int32_t degree, int32_t regularity, double c_pen, int32_t* n_out,
+                                  double* K) {
+  if (!n_out) return fail(FD_E_ARG, "fd_nitsche_stiffness_1d: NULL n_out");
+  int m = 0;
+  if (fdh::nitsche_stiffness_1d(n_el, degree, regularity, c_pen, &m, K) != 0)
+    return fail(FD_E_ARG, "fd_nitsche_stiffness_1d: invalid n_el/degree/regularity or c_pen < 0");
   *n_out = m;
   return FD_OK;
 }
@@ -1007,8 +1071,86 @@ size_t fd_workspace_bytes(fd_plan plan, int32_t nrhs) {
   return 0;
 }
 
+fd_status fd_setup_mass_banded(int32_t ndim, const int32_t* n, const double* const* M, fd_precision prec,
+                               fd_plan* out) {
+  if (!out) return fail(FD_E_ARG, "fd_setup_mass_banded: NULL out");
+  *out = nullptr;
+  if (ndim != 2 && ndim != 3) return fail(FD_E_ARG, "fd_setup_mass_banded: ndim must be 2 or 3");
+  if (!n || !M) return fail(FD_E_ARG, "fd_setup_mass_banded: NULL n or M");
+  if (int(prec) < 0 || int(prec) > 6) return fail(FD_E_ARG, "fd_setup_mass_banded: unknown precision");
+  auto p = new (std::nothrow) fd_plan_s();
+  if (!p) return fail(FD_E_NOMEM, "fd_setup_mass_banded: host allocation");
+  p->ndim = ndim;
+  p->prec = int(prec);
+  p->mass_only = true;
+  p->banded = true;
+  p->N = 1;
+  std::vector<double> fac[3];
+  const bool f64 = io_is_f64(p->prec);
+  const size_t eb = f64 ? 8 : 4;
+  size_t offs[3], total = 0;
+  for (int i = 0; i < ndim; ++i) {
+    if (n[i] < 2 || n[i] > fdk::kMaxN || !M[i]) {
+      delete p;
+      return fail(FD_E_ARG, "fd_setup_mass_banded: each n[i] must be in [2, 256] with M[i] given");
+    }
+    p->n[i] = n[i];
+    p->N *= n[i];
+    int bw = 0;
+    const int rc0 = fdh::band_cholesky(n[i], M[i], fdk::kMaxBand, &bw, nullptr, nullptr);
+    if (rc0 != 0) {
+      delete p;
+      return fail(FD_E_ARG, "fd_setup_mass_banded: M[" + std::to_string(i) + "] asymmetric or bandwidth above 16");
+    }
+    p->bw[i] = bw;
+    fac[i].assign(size_t(bw + 1) * n[i], 0.0);
+    // rows 1..bw of the band and, in row 0, the reciprocal diagonal
+    const int rc = fdh::band_cholesky(n[i], M[i], fdk::kMaxBand, &bw, fac[i].data(), fac[i].data());
+    if (rc != 0) {
+      delete p;
+      return fail(FD_E_NOTSPD, "fd_setup_mass_banded: M[" + std::to_string(i) + "] is not positive definite");
+    }
+    offs[i] = total;
+    total += (fac[i].size() * eb + 255) & ~size_t(255);
+  }
+  if (p->N >= (int64_t(1) << 28)) {
+    delete p;
+    return fail(FD_E_ARG, "fd_setup_mass_banded: prod(n) must be below 2^28");
+  }
+  hipError_t e = hipGetDevice(&p->device);
+  if (e == hipSuccess) e = hipMalloc(&p->dev, total);
+  if (e != hipSuccess) {
+    p->dev = nullptr;
+    delete p;
+    return e == hipErrorOutOfMemory ? fail(FD_E_NOMEM, "fd_setup_mass_banded: device memory")
+                                    : hip_fail(e, "fd_setup_mass_banded");
+  }
+  p->dev_bytes = total;
+  std::vector<unsigned char> host(total, 0);
+  for (int i = 0; i < ndim; ++i) {
+    unsigned char* dst = host.data() + offs[i];
+    for (size_t k = 0; k < fac[i].size(); ++k) {
+      if (f64) {
+        std::memcpy(dst + 8 * k, &fac[i][k], 8);
+      } else {
+        const float v = float(fac[i][k]);
+        std::memcpy(dst + 4 * k, &v, 4);
+      }
+    }
+    p->bfac[i] = static_cast<unsigned char*>(p->dev) + offs[i];
+  }
+  e = hipMemcpy(p->dev, host.data(), total, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    fd_destroy(p);
+    return hip_fail(e, "fd_setup_mass_banded: upload");
+  }
+  *out = p;
+  return FD_OK;
+}
+
 fd_status fd_plan_factors(fd_plan plan, int32_t dir, double* U, double* d) {
   if (!plan || dir < 0 || dir >= plan->ndim) return fail(FD_E_ARG, "fd_plan_factors: bad plan or direction");
+  if (plan->banded) return fail(FD_E_UNSUPPORTED, "fd_plan_factors: a banded mass plan holds no eigenvectors");
   const int m = plan->n[dir];
   if (U) std::memcpy(U, plan->U[dir].data(), sizeof(double) * m * m);
   if (d) std::memcpy(d, plan->d[dir].data(), sizeof(double) * m);

@@ -198,6 +198,85 @@ int assemble_1d(int n_el, int degree, int regularity, int dirichlet, int npts, c
   return 0;
 }
 
+// Nitsche-modified stiffness of the RT velocity blocks (Sec. 5, the factor
+// K~ below eq. prec3D_RT): the full-space stiffness plus the one-direction
+// face terms of the parametric Nitsche form,
+//   K~_ls = K_ls - [b'_l b_s + b'_s b_l]_0^1 + 2 (c_pen / h) (b_l b_s (1) + b_l b_s (0)),
+// h = 1 / n_el. End values come from the first and the last knot span (the
+// last one closed at x = 1).
+int nitsche_stiffness_1d(int n_el, int degree, int regularity, double c_pen, int* m_out, double* K) {
+  if (!(c_pen >= 0.0)) return 1;
+  int m = 0;
+  if (assemble_1d(n_el, degree, regularity, 0, 0, nullptr, nullptr, &m, nullptr, nullptr) != 0) return 1;
+  *m_out = m;
+  if (!K) return 0;
+  if (assemble_1d(n_el, degree, regularity, 0, 0, nullptr, nullptr, &m, K, nullptr) != 0) return 1;
+  const std::vector<double> t = knots_open_uniform(n_el, degree, regularity);
+  const double h = 1.0 / n_el;
+  double N[32], dN[32];
+  // (span, point, sign of the outer normal's contribution)
+  const int spans[2] = {degree, m - 1};
+  const double xs[2] = {0.0, 1.0}, sg[2] = {-1.0, 1.0};
+  for (int e = 0; e < 2; ++e) {
+    nonzero_basis_ders(t, spans[e], degree, xs[e], N, dN);
+    const int f0 = spans[e] - degree;
+    for (int a = 0; a <= degree; ++a)
+      for (int b = 0; b <= degree; ++b) {
+        const int l = f0 + a, s = f0 + b;
+        K[l + size_t(m) * s] += -sg[e] * (dN[a] * N[b] + dN[b] * N[a]) + 2.0 * c_pen / h * N[a] * N[b];
+      }
+  }
+  return 0;
+}
+
+// Banded Cholesky factor of a symmetric positive definite matrix (the
+// route of Sec. 5.2 for P_Q: each M_i has bandwidth degree, so its solve is
+// O(degree n)). M: n x n column-major; the bandwidth b is the largest |i - j|
+// with M_ij != 0. L (lower, M = L L^T) is returned as band[j * n + i] =
+// L(i, i - j) for j = 1..b and rdiag[i] = 1 / L(i, i). 0, 1 (arguments,
+// asymmetry or b > max_band) or 2 (not positive definite).
+int band_cholesky(int n, const double* M, int max_band, int* b_out, double* band, double* rdiag) {
+  if (n < 1 || !M || max_band < 0) return 1;
+  int b = 0;
+  double amax = 0.0;
+  for (int c = 0; c < n; ++c)
+    for (int r = 0; r < n; ++r) amax = std::max(amax, std::fabs(M[r + size_t(n) * c]));
+  for (int c = 0; c < n; ++c)
+    for (int r = 0; r < n; ++r) {
+      const double v = M[r + size_t(n) * c];
+      if (std::fabs(v - M[c + size_t(n) * r]) > 1e-12 * amax) return 1;
+      if (v != 0.0) b = std::max(b, std::abs(r - c));
+    }
+  if (b > max_band) return 1;
+  *b_out = b;
+  if (!band || !rdiag) return 0;
+  // dense lower factor restricted to the band, row by row
+  std::vector<double> L(size_t(n) * (b + 1), 0.0);  // L[i * (b+1) + j] = L(i, i - j)
+  for (int i = 0; i < n; ++i) {
+    for (int j = std::min(b, i); j >= 0; --j) {
+      const int k = i - j;  // column
+      double s = M[i + size_t(n) * k];
+      for (int t = 1; t <= b; ++t) {
+        // sum over columns c < k inside both bands: L(i, c) L(k, c), c = k - t
+        const int c = k - t;
+        if (c < 0 || i - c > b) continue;
+        s -= L[size_t(i) * (b + 1) + (i - c)] * L[size_t(k) * (b + 1) + (k - c)];
+      }
+      if (j == 0) {
+        if (!(s > 0.0)) return 2;
+        L[size_t(i) * (b + 1)] = std::sqrt(s);
+      } else {
+        L[size_t(i) * (b + 1) + j] = s / L[size_t(k) * (b + 1)];
+      }
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    rdiag[i] = 1.0 / L[size_t(i) * (b + 1)];
+    for (int j = 1; j <= b; ++j) band[size_t(j) * n + i] = L[size_t(i) * (b + 1) + j];
+  }
+  return 0;
+}
+
 // ------------------------------------------------------------------ eigensolve
 
 // Symmetric eigenproblem by cyclic Jacobi (row-cyclic ordering), with the

@@ -19,6 +19,17 @@ void element_quadrature(int n_el, int npts, double* xq, double* wq);
 int assemble_1d(int n_el, int degree, int regularity, int dirichlet, int npts, const double* tau_q,
                 const double* mu_q, int* m_out, double* K, double* M);
 
+// Nitsche-modified stiffness K~ of the RT velocity blocks over all m functions
+// of the space (column-major m x m). 0 on success, 1 on bad arguments; K may
+// be null to query m.
+int nitsche_stiffness_1d(int n_el, int degree, int regularity, double c_pen, int* m_out, double* K);
+
+// Banded Cholesky M = L L^T of an SPD matrix of bandwidth b <= max_band:
+// band[j*n + i] = L(i, i-j) (j = 1..b; row j = 0 unused), rdiag[i] = 1/L(i,i).
+// band/rdiag may be null to query b. 0, 1 (arguments, asymmetry, b too
+// large) or 2 (not positive definite).
+int band_cholesky(int n, const double* M, int max_band, int* b_out, double* band, double* rdiag);
+
 // Generalized eigendecomposition K U = M U diag(d), U^T M U = I, d ascending.
 // K may be null (d = 0). Returns 0, 1 (bad argument / asymmetric) or
 // 2 (M not positive definite); *why names the failure.

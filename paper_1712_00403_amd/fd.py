@@ -20,8 +20,8 @@ STATUS_NAMES = {0: "FD_OK", 1: "FD_E_ARG", 2: "FD_E_NOTSPD", 3: "FD_E_NOMEM", 4:
                 5: "FD_E_UNSUPPORTED"}
 
 # every symbol declared in include/fd.h
-EXPORTS = ("fd_assemble_1d", "fd_quadrature_1d", "fd_factor_1d", "fd_geometry_coefficients",
-           "fd_separable_factors", "fd_operator_diagonal", "fd_setup", "fd_destroy",
+EXPORTS = ("fd_assemble_1d", "fd_nitsche_stiffness_1d", "fd_quadrature_1d", "fd_factor_1d", "fd_geometry_coefficients",
+           "fd_separable_factors", "fd_operator_diagonal", "fd_setup", "fd_setup_mass_banded", "fd_destroy",
            "fd_plan_size", "fd_plan_device_bytes", "fd_workspace_bytes", "fd_plan_factors", "fd_apply",
            "fd_apply_batched", "fd_batch_create", "fd_batch_apply", "fd_batch_tune", "fd_batch_set_config",
            "fd_batch_info", "fd_batch_check", "fd_batch_destroy", "fd_apply_persistent_static", "fd_timing_enable", "fd_timing_read", "fd_timing_launches", "fd_last_error")
@@ -59,6 +59,8 @@ def lib():
     L.fd_last_error.restype = ctypes.c_char_p
     L.fd_assemble_1d.argtypes = [ctypes.c_int32] * 5 + [c_dp, c_dp, ctypes.POINTER(ctypes.c_int32), c_dp, c_dp]
     L.fd_quadrature_1d.argtypes = [ctypes.c_int32, ctypes.c_int32, c_dp, c_dp]
+    L.fd_nitsche_stiffness_1d.argtypes = [ctypes.c_int32] * 3 + [ctypes.c_double, ctypes.POINTER(ctypes.c_int32),
+                                                                  c_dp]
     L.fd_factor_1d.argtypes = [ctypes.c_int32, c_dp, c_dp, c_dp, c_dp]
     L.fd_geometry_coefficients.argtypes = [ctypes.c_int32, ctypes.c_int64, c_dp, c_dp, ctypes.c_int32, c_dp, c_dp]
     L.fd_separable_factors.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), c_dp, ctypes.c_int64,
@@ -67,6 +69,8 @@ def lib():
         [c_dp, c_dp]
     L.fd_setup.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(c_dp),
                            ctypes.POINTER(c_dp), c_dp, c_dp, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]
+    L.fd_setup_mass_banded.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(c_dp),
+                                       ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]
     L.fd_destroy.argtypes = [ctypes.c_void_p]
     L.fd_plan_size.argtypes = [ctypes.c_void_p]
     L.fd_plan_size.restype = ctypes.c_int64
@@ -96,8 +100,8 @@ def lib():
     L.fd_timing_read.argtypes = [c_dp, ctypes.POINTER(ctypes.c_int32)]
     L.fd_timing_launches.argtypes = [ctypes.c_int32, ctypes.POINTER(FDLaunchTime), ctypes.POINTER(ctypes.c_int32)]
     L.fd_timing_launches.restype = ctypes.c_int
-    for name in ("fd_timing_enable", "fd_timing_read", "fd_assemble_1d", "fd_quadrature_1d", "fd_factor_1d",
-                 "fd_geometry_coefficients", "fd_separable_factors", "fd_operator_diagonal", "fd_setup", "fd_destroy",
+    for name in ("fd_timing_enable", "fd_timing_read", "fd_assemble_1d", "fd_nitsche_stiffness_1d", "fd_quadrature_1d", "fd_factor_1d",
+                 "fd_geometry_coefficients", "fd_separable_factors", "fd_operator_diagonal", "fd_setup", "fd_setup_mass_banded", "fd_destroy",
                  "fd_plan_factors", "fd_apply", "fd_apply_batched"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -133,6 +137,17 @@ def assemble_1d(n_el, degree, regularity, dirichlet, npts=0, tau=None, mu=None):
                             ctypes.byref(m), K.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                             M.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     return np.ascontiguousarray(K), np.ascontiguousarray(M)
+
+
+def nitsche_stiffness_1d(n_el, degree, regularity, c_pen):
+    """The RT blocks' Nitsche-modified stiffness K~ over all functions of the space (fd_nitsche_stiffness_1d)."""
+    L = lib()
+    m = ctypes.c_int32(0)
+    _check(L.fd_nitsche_stiffness_1d(n_el, degree, regularity, float(c_pen), ctypes.byref(m), None))
+    K = np.zeros((m.value, m.value), order="F")
+    _check(L.fd_nitsche_stiffness_1d(n_el, degree, regularity, float(c_pen), ctypes.byref(m),
+                                     K.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return np.ascontiguousarray(K)
 
 
 def quadrature_1d(n_el, npts):
@@ -214,7 +229,9 @@ def operator_diagonal(n_el, degree, regularity, dirichlet, npts, coef, order):
 class Plan:
     """One Kronecker-sum block on the device (fd_setup / fd_destroy)."""
 
-    def __init__(self, Ks, Ms, weights=None, diag_target=None, precision="f64"):
+    def __init__(self, Ks, Ms, weights=None, diag_target=None, precision="f64", banded=False):
+        """``banded``: a mass-only plan (Ks None, no weights or diag_target) applied by banded
+        Cholesky solves per mode (fd_setup_mass_banded) instead of the FD form."""
         L = lib()
         ndim = len(Ms)
         self.ndim = ndim
@@ -231,7 +248,13 @@ class Plan:
         w = None if weights is None else _f64c(weights)
         dt = None if diag_target is None else _f64c(diag_target).ravel()
         h = ctypes.c_void_p(0)
-        _check(L.fd_setup(ndim, narr, Karr, Marr, _dp(w), _dp(dt), self.prec_id, ctypes.byref(h)))
+        self.banded = bool(banded)
+        if self.banded:
+            if Ks is not None or diag_target is not None:
+                raise ValueError("a banded plan is mass-only and unscaled")
+            _check(L.fd_setup_mass_banded(ndim, narr, Marr, self.prec_id, ctypes.byref(h)))
+        else:
+            _check(L.fd_setup(ndim, narr, Karr, Marr, _dp(w), _dp(dt), self.prec_id, ctypes.byref(h)))
         self.handle = h.value
         self.device = _current_device()
         self.N = int(L.fd_plan_size(self.handle))

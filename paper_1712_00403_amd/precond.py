@@ -15,10 +15,12 @@ from . import fd
 
 
 def block_factors(spec):
-    """(Ks, Ms) of one block from the library's assembly (Ks None for mass-only)."""
+    """(Ks, Ms) of one block from the library's assembly (Ks None for mass-only; Nitsche factors where named)."""
     Ks, Ms = [], []
     for f in spec.dirs:
         K, M = fd.assemble_1d(f.n_el, f.degree, f.regularity, f.dirichlet)
+        if f.nitsche > 0:  # the RT blocks' Nitsche-modified stiffness
+            K = fd.nitsche_stiffness_1d(f.n_el, f.degree, f.regularity, f.nitsche)
         Ks.append(K)
         Ms.append(M)
     return (None if spec.mass_only else Ks), Ms
@@ -32,7 +34,12 @@ class BlockPreconditioner:
     scalings, e.g. with those of the coefficient-aware blocks (``geometry``).
     """
 
-    def __init__(self, problem, precision="f64", diag_targets=None, factors=None, weights=None):
+    def __init__(self, problem, precision="f64", diag_targets=None, factors=None, weights=None,
+                 pressure="fd"):
+        """``pressure``: "fd" applies the unscaled mass-only block by FD with Lambda = I,
+        "banded" by banded Cholesky solves per mode (the O(p n_Q) route of Sec. 5.2)."""
+        if pressure not in ("fd", "banded"):
+            raise ValueError("pressure route must be 'fd' or 'banded'")
         self.problem = problem
         self.precision = precision
         self.plans = []
@@ -41,7 +48,9 @@ class BlockPreconditioner:
             Ks, Ms = factors[bi] if factors is not None else block_factors(spec)
             dt = None if diag_targets is None else diag_targets[bi]
             w = np.asarray(spec.weights if weights is None else weights[bi], dtype=np.float64)
-            plan = fd.Plan(Ks, Ms, weights=w, diag_target=dt, precision=precision)
+            banded = pressure == "banded" and Ks is None and dt is None
+            plan = fd.Plan(Ks, Ms, weights=None if banded else w, diag_target=dt, precision=precision,
+                           banded=banded)
             self.plans.append(plan)
             self.sizes.append(plan.N)
         self.offsets = np.concatenate([[0], np.cumsum(self.sizes)]).astype(np.int64)

@@ -19,11 +19,17 @@ import numpy as np
 
 @dataclass(frozen=True)
 class Factor1D:
-    """One univariate space: uniform mesh of [0,1] with n_el elements."""
+    """One univariate space: uniform mesh of [0,1] with n_el elements.
+
+    ``nitsche`` > 0 names the penalty C_pen of a Nitsche-modified stiffness
+    factor (the RT blocks' K~ over all functions of the space); 0 for the
+    plain stiffness.
+    """
     n_el: int
     degree: int
     regularity: int
     dirichlet: bool
+    nitsche: float = 0.0
 
 
 @dataclass(frozen=True)
@@ -40,7 +46,7 @@ class BlockSpec:
 
 @dataclass(frozen=True)
 class Problem:
-    """A Taylor-Hood patch: d velocity blocks then the pressure block."""
+    """A Taylor-Hood or Raviart-Thomas patch: d velocity blocks then the pressure block."""
     ndim: int
     n_el: Tuple[int, ...]
     p: int
@@ -61,6 +67,29 @@ def taylor_hood_problem(n_el, p, unit_weights=False):
     for k in range(d):
         w = tuple(1.0 if (unit_weights or i != k) else 2.0 for i in range(d))
         blocks.append(BlockSpec(f"u{k + 1}", vel, w, False))
+    blocks.append(BlockSpec("p", pres, tuple(1.0 for _ in range(d)), True))
+    return Problem(d, n_el, p, tuple(blocks))
+
+
+def raviart_thomas_problem(n_el, p, c_pen=None):
+    """Blocks of P_D for an RT patch (Sec. 2.2.2, eq. prec3D_RT) with ``n_el`` elements per direction.
+
+    Velocity block k: direction k has degree p + 1, regularity p (alpha + 1)
+    and drops its first and last function (normal component zero on the
+    faces normal to e_k), with weight 2; every other direction has degree p,
+    regularity p - 1 and all functions, with the Nitsche factor of penalty
+    c_pen (default 5 (alpha + 1) = 5 p, the value of the experiments).
+    The pressure block is that of TH (degree p, regularity p - 1).
+    """
+    n_el = tuple(int(x) for x in n_el)
+    d = len(n_el)
+    c = 5.0 * p if c_pen is None else float(c_pen)
+    blocks = []
+    for k in range(d):
+        dirs = tuple(Factor1D(n_el[j], p + 1, p, True) if j == k else Factor1D(n_el[j], p, p - 1, False, c)
+                     for j in range(d))
+        blocks.append(BlockSpec(f"u{k + 1}", dirs, tuple(2.0 if j == k else 1.0 for j in range(d)), False))
+    pres = tuple(Factor1D(n_el[i], p, p - 1, False) for i in range(d))
     blocks.append(BlockSpec("p", pres, tuple(1.0 for _ in range(d)), True))
     return Problem(d, n_el, p, tuple(blocks))
 

@@ -5,6 +5,7 @@
 // separable fit and the operator diagonals in 2D and 3D; and the argument
 // checks of each routine. Prints "ok" and exits 0 when every property checked
 // here holds; the sanitizers abort on the first memory or UB error.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -59,6 +60,43 @@ int main() {
   CHECK(fdh::assemble_1d(4, 0, 0, 0, 0, nullptr, nullptr, &m, nullptr, nullptr) == 1);
   CHECK(fdh::assemble_1d(4, 3, 3, 0, 0, nullptr, nullptr, &m, nullptr, nullptr) == 1);
   CHECK(fdh::assemble_1d(4, 3, 1, 0, 17, nullptr, nullptr, &m, nullptr, nullptr) == 1);
+
+  // ---- Nitsche-modified stiffness: symmetric, argument checks
+  for (int deg = 1; deg <= 6; ++deg)
+    for (int n_el : {1, 2, 9}) {
+      CHECK(fdh::nitsche_stiffness_1d(n_el, deg, deg - 1, 5.0 * deg, &m, nullptr) == 0);
+      std::vector<double> K(size_t(m) * m);
+      CHECK(fdh::nitsche_stiffness_1d(n_el, deg, deg - 1, 5.0 * deg, &m, K.data()) == 0);
+      CHECK(sym_err(m, K) < 1e-13);
+    }
+  CHECK(fdh::nitsche_stiffness_1d(3, 2, 1, -1.0, &m, nullptr) == 1);
+
+  // ---- banded Cholesky of mass matrices: L L^T = M on the band
+  for (int deg = 1; deg <= 6; ++deg)
+    for (int n_el : {1, 4, 11}) {
+      CHECK(fdh::assemble_1d(n_el, deg, deg - 1, 0, 0, nullptr, nullptr, &m, nullptr, nullptr) == 0);
+      std::vector<double> M(size_t(m) * m);
+      CHECK(fdh::assemble_1d(n_el, deg, deg - 1, 0, 0, nullptr, nullptr, &m, nullptr, M.data()) == 0);
+      int bw = -1;
+      CHECK(fdh::band_cholesky(m, M.data(), 16, &bw, nullptr, nullptr) == 0 && bw == std::min(deg, m - 1));
+      std::vector<double> fac(size_t(bw + 1) * m);
+      CHECK(fdh::band_cholesky(m, M.data(), 16, &bw, fac.data(), fac.data()) == 0);
+      auto L = [&](int i, int j) { return i == j ? 1.0 / fac[i] : (i - j >= 1 && i - j <= bw ? fac[size_t(i - j) * m + i] : 0.0); };
+      double err = 0.0;
+      for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) {
+          double s = 0.0;
+          for (int c = 0; c < m; ++c) s += L(i, c) * L(j, c);
+          err = std::fmax(err, std::fabs(s - M[i + size_t(m) * j]));
+        }
+      CHECK(err < 1e-14);
+    }
+  {
+    std::vector<double> B = {1.0, 2.0, 2.0, 1.0}, f(4);
+    int bw = 0;
+    CHECK(fdh::band_cholesky(2, B.data(), 16, &bw, f.data(), f.data()) == 2);
+    CHECK(fdh::band_cholesky(2, B.data(), 0, &bw, nullptr, nullptr) == 1);
+  }
 
   // ---- eigensolve: U^T M U = I, K U = M U diag(d) for orders up to 256
   for (int n_el : {1, 3, 16, 64, 127}) {

@@ -112,3 +112,28 @@ def test_taylor_hood_sizes_from_library(fd):
     assert fd.assemble_1d(64, 3, 2, False)[0].shape[0] == 67
     assert fd.assemble_1d(96, 5, 3, True)[0].shape[0] == 194
     assert fd.assemble_1d(96, 4, 3, False)[0].shape[0] == 100
+
+
+@pytest.mark.parametrize("n_el,deg,reg", [(1, 1, 0), (4, 2, 1), (7, 3, 2), (5, 4, 3), (3, 5, 2), (16, 3, 1)])
+def test_nitsche_stiffness_matches_oracle(fd, n_el, deg, reg):
+    """The library's K~ of the RT blocks against the oracle's (both from the definition below eq. prec3D_RT)."""
+    from oracle.assemble import nitsche_stiffness_1d
+    c = 5.0 * (reg + 1)
+    K = fd.nitsche_stiffness_1d(n_el, deg, reg, c)
+    Ko = nitsche_stiffness_1d(n_el, deg, reg, c)
+    np.testing.assert_allclose(K, Ko, rtol=0, atol=1e-12 * np.abs(Ko).max())
+    with pytest.raises(fd.FDError):
+        fd.nitsche_stiffness_1d(n_el, deg, reg, -1.0)
+
+
+def test_raviart_thomas_sizes_from_library(fd):
+    """RT block sizes: n_el + p - 1 in the component's own direction, n_el + p in the others."""
+    from paper_1712_00403_amd import workloads
+    from paper_1712_00403_amd.precond import block_factors
+    prob = workloads.raviart_thomas_problem((5, 7, 6), 3)
+    for k in range(3):
+        Ks, Ms = block_factors(prob.blocks[k])
+        assert [M.shape[0] for M in Ms] == [n + 3 - 1 if j == k else n + 3 for j, n in enumerate((5, 7, 6))]
+        assert [K.shape[0] for K in Ks] == [M.shape[0] for M in Ms]
+    _, Mp = block_factors(prob.blocks[3])
+    assert [M.shape[0] for M in Mp] == [8, 10, 9]

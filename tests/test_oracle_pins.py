@@ -313,3 +313,98 @@ def test_scaled_variant_brute_force():
     P = brute.assemble_operator(Ks, Ms).toarray()
     PG = np.diag(1 / s) @ P @ np.diag(1 / s)
     assert np.allclose(PG @ z, r, atol=1e-10 * np.abs(r).max())
+
+
+# ---------------------------------------------------------------- Raviart-Thomas blocks (Sec. 2.2.2, eq. prec3D_RT)
+
+def test_nitsche_stiffness_degree1_by_hand():
+    """K~ of degree-1 hat functions, worked by hand from its definition below eq. prec3D_RT.
+
+    Hats on n_el uniform elements (h = 1/n_el), all functions kept: K = h^-1
+    tridiag(-1, 2, -1) with end entries 1. End values: b_1(0) = 1,
+    b'_1(0) = -1/h, b'_2(0) = 1/h; b_m(1) = 1, b'_m(1) = 1/h, b'_{m-1}(1) = -1/h.
+    So K~_11 = K~_mm = (1 - 2 + 2 C) / h and K~_12 = K~_{m-1,m} = (-1 + 1) / h = 0;
+    the interior rows are those of K.
+    """
+    from oracle.assemble import nitsche_stiffness_1d
+    n_el, C = 5, 1.75
+    h = 1.0 / n_el
+    Kt = nitsche_stiffness_1d(n_el, 1, 0, C)
+    m = n_el + 1
+    E = (np.diag(np.full(m, 2.0)) - np.diag(np.ones(m - 1), 1) - np.diag(np.ones(m - 1), -1)) / h
+    E[0, 0] = E[-1, -1] = (2.0 * C - 1.0) / h
+    E[0, 1] = E[1, 0] = E[-1, -2] = E[-2, -1] = 0.0
+    np.testing.assert_allclose(Kt, E, rtol=0, atol=1e-12 / h)
+
+
+@pytest.mark.parametrize("deg,reg,n_el", [(2, 1, 4), (3, 2, 3), (3, 1, 5), (4, 3, 2)])
+def test_nitsche_stiffness_quadratic_form_of_polynomials(deg, reg, n_el):
+    """u^T K~ u = int u'^2 - 2 (u'(1) u(1) - u'(0) u(0)) + 2 (C/h) (u(1)^2 + u(0)^2) for u in the space.
+
+    The coefficients of u = x^2 - 3x + 2 (in every space of degree >= 2) are
+    its L2 projection M c = (int b_l u); the right side is evaluated in
+    closed form: int (2x - 3)^2 = 13/3, u(0) = 2, u'(0) = -3, u(1) = 0.
+    """
+    from oracle.assemble import assemble_1d, nitsche_stiffness_1d
+    from oracle.bspline import basis_values, element_quadrature, open_uniform_knots
+    C = 3.0
+    h = 1.0 / n_el
+    knots = open_uniform_knots(n_el, deg, reg)
+    xq, wq = element_quadrature(n_el, deg + 3)
+    B = basis_values(knots, deg, xq.ravel())
+    u = xq.ravel() ** 2 - 3 * xq.ravel() + 2
+    _, M = assemble_1d(n_el, deg, reg, False)
+    c = np.linalg.solve(M, B @ (wq.ravel() * u))
+    Kt = nitsche_stiffness_1d(n_el, deg, reg, C)
+    expect = 13.0 / 3.0 - 2.0 * (0.0 - (-3.0) * 2.0) + 2.0 * C / h * (0.0 + 4.0)
+    assert c @ Kt @ c == pytest.approx(expect, rel=1e-11)
+
+
+@pytest.mark.parametrize("n_el,p", [((2, 3, 2), 1), ((2, 2, 3), 2), ((3, 2), 2), ((2, 2, 2), 3)])
+def test_rt_kronecker_blocks_equal_variational_definition(n_el, p):
+    """eq. prec3D_RT (and its 2D analogue) against the block assembled from a^ + sigma^ (eq. precVrt)."""
+    from oracle.assemble import raviart_thomas_velocity_1d, rt_penalty
+    from oracle.brute import assemble_operator, rt_velocity_block_variational
+    for k in range(len(n_el)):
+        Ks, Ms, w = raviart_thomas_velocity_1d(n_el, p, k)
+        P = assemble_operator(Ks, Ms, w).toarray()
+        V = rt_velocity_block_variational(n_el, p, k, rt_penalty(p))
+        np.testing.assert_allclose(P, V, rtol=0, atol=1e-10 * np.abs(V).max())
+
+
+def test_rt_block_with_misplaced_factors_is_detected():
+    """Swapping which directions carry the Nitsche factors (or the weight 2) changes the block."""
+    from oracle.assemble import raviart_thomas_velocity_1d, rt_penalty
+    from oracle.brute import assemble_operator, rt_velocity_block_variational
+    n_el, p, k = (2, 3, 2), 2, 0
+    V = rt_velocity_block_variational(n_el, p, k, rt_penalty(p))
+    Ks, Ms, w = raviart_thomas_velocity_1d(n_el, p, k)
+    w_bad = np.roll(w, 1)
+    assert np.abs(assemble_operator(Ks, Ms, w_bad).toarray() - V).max() > 1e-3 * np.abs(V).max()
+    V_half_pen = rt_velocity_block_variational(n_el, p, k, 0.5 * rt_penalty(p))
+    assert np.abs(V_half_pen - V).max() > 1e-3 * np.abs(V).max()
+
+
+@pytest.mark.parametrize("n_el,p", [((4, 3, 5), 1), ((3, 4, 2), 2), ((2, 3, 3), 3), ((6, 4), 4)])
+def test_rt_fd_equals_brute_force(n_el, p):
+    """FD (Algorithm 1) on the RT blocks: anisotropic per-direction spaces, solved exactly."""
+    from oracle.assemble import raviart_thomas_velocity_1d
+    from oracle.brute import solve
+    from oracle.fd import FDFactors, fd_apply
+    rng = np.random.default_rng(7)
+    for k in range(len(n_el)):
+        Ks, Ms, w = raviart_thomas_velocity_1d(n_el, p, k)
+        f = FDFactors(Ks, Ms, w)
+        r = rng.standard_normal(int(np.prod(f.n)))
+        z = fd_apply(f, r)
+        zb = solve(Ks, Ms, r, w)
+        assert np.linalg.norm(z - zb) / np.linalg.norm(zb) < 1e-11
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
+def test_rt_nitsche_factor_is_spd_at_the_experiment_penalty(p):
+    """With C_pen = 5 (alpha + 1) the Nitsche factor is positive definite (so Lambda > 0)."""
+    from oracle.assemble import nitsche_stiffness_1d, rt_penalty
+    for n_el in (1, 2, 8, 33):
+        Kt = nitsche_stiffness_1d(n_el, p, p - 1, rt_penalty(p))
+        assert np.linalg.eigvalsh(0.5 * (Kt + Kt.T)).min() > 0
