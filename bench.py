@@ -198,8 +198,10 @@ def main():
     traffic = recorded_traffic(head_prec)
     roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": traffic,
-                "kernel": f"fd_pass3_kernel<{'0,9,2,true' if head_prec == 'f64' else '1,9,2,true'}> (fused last-mode pass, "
-                          "velocity blocks 129^3 x 3 x 16 residuals)",
+                "kernel": ("fd_pass3_kernel<0,9,2,true>" if head_prec == "f64" else
+                           "fd_pass3_kernel<1,9,2,true>" if head_prec == "f32" else
+                           f"the {head_prec} class's fused pass kernel") +
+                          " (fused last-mode pass, velocity blocks 129^3 x 3 x 16 residuals)",
                 "algorithmic_gflop_per_launch": dom_flops / 1e9, "avg_launch_ms": dom_ms,
                 "algorithmic_bytes_per_launch": nrhs * 3 * 129 ** 3 * (16 if head_prec == "f64" else 8),
                 "kernel_source_hash": kernel_source_hash()}

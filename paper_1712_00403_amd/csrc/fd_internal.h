@@ -131,6 +131,24 @@ hipError_t batch_resident(int prec, size_t smem, int* per_cu);
 hipError_t batch_launch(const BatchArgs& args, int prec, int grid, size_t smem, hipStream_t stream);
 hipError_t batch_reset(uint32_t* barrier, int32_t* error, hipStream_t stream);
 
+// ---- banded Cholesky solves of the pressure-mass block (fd_banded.hip)
+struct BandDesc {
+  const void* in;       // I/O type: double for FP64 plans, float otherwise
+  void* out;
+  const void* fac;      // (bw + 1) x n in the compute type: row 0 = 1 / L(i,i), row j = L(i, i - j)
+  int64_t ld;           // elements between residual vectors
+  int32_t A, n, B;      // tensor view of the mode (as PassDesc)
+  int32_t nrhs, bw;
+  int32_t tiles_per_rhs;
+};
+struct BandArgs {
+  BandDesc u;
+};
+constexpr int kMaxBand = 16;
+size_t band_lds_bytes(int n, int bw, bool f64);
+int band_tiles_per_rhs(int64_t pencils);
+hipError_t launch_band(const BandArgs& args, bool f64, hipStream_t stream);
+
 size_t plain_bytes(int n, int prec);
 void plain_factor(int n, const double* F, int prec, void* dst);
 // Padded factor image of the pipelined kernels (FP64, FP32, BF16, FP16
