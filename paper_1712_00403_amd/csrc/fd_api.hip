@@ -311,6 +311,7 @@ fd_status run_work(int count, const fd_work* work, hipStream_t stream) {
           if (fam == 2) ok = fdk::v2_plan(prec, mode, max_n, max_mt, &bucket, &chunk, &smem);
           if (!ok) return fail(FD_E_HIP, "internal: kernel plan changed");
           fdk::PassArgs args;
+          args.lam_lds = 0;
           args.count = 0;
           args.total_tiles = 0;
           int launch_mt = 1;
@@ -709,6 +710,18 @@ fd_status fd_nitsche_stiffness_1d(int32_t n_el, int32_t degree, int32_t regulari
   if (fdh::nitsche_stiffness_1d(n_el, degree, regularity, c_pen, &m, K) != 0)
     return fail(FD_E_ARG, "fd_nitsche_stiffness_1d: invalid n_el/degree/regularity or c_pen < 0");
   *n_out = m;
+  return FD_OK;
+}
+
+fd_status fd_mixed_1d(int32_t n_el, int32_t deg_a, int32_t reg_a, int32_t da, int32_t deg_b, int32_t reg_b,
+                      int32_t db, int32_t npts, int32_t* ma, int32_t* mb, double* X) {
+  if (!ma || !mb) return fail(FD_E_ARG, "fd_mixed_1d: NULL size outputs");
+  int a = 0, b = 0;
+  if (npts <= 0) npts = std::max(deg_a, deg_b) + 2;
+  if (fdh::mixed_1d(n_el, deg_a, reg_a, da, deg_b, reg_b, db, npts, &a, &b, X) != 0)
+    return fail(FD_E_ARG, "fd_mixed_1d: invalid spaces, derivative orders or npts");
+  *ma = a;
+  *mb = b;
   return FD_OK;
 }
 

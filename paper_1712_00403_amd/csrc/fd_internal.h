@@ -91,8 +91,13 @@ struct BatchArgs {
 struct PassArgs {
   int32_t count;
   int32_t total_tiles;
+  int32_t lam_lds;      // pipelined divide passes: 1 = the weighted eigenvalues of every unit sit in LDS
   PassDesc u[kMaxDesc];
 };
+
+// LDS bytes of the weighted-eigenvalue tables of a divide pass (w_0 d_0, w_1 d_1
+// and w_l d_l of every unit, FP64), placed after the pipeline ring.
+size_t lam_table_bytes(const PassArgs& args);
 
 // Storage/compute class of a plan: 0 = FP64 MFMA, 1 = FP32 MFMA,
 // 2 = BF16 MFMA, 3 = FP16 MFMA, 4 = BF16 split, 5 = FP16 split.

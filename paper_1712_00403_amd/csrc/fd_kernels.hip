@@ -211,6 +211,15 @@ hipError_t batch_reset(uint32_t* barrier, int32_t* error, hipStream_t stream) {
   return hipGetLastError();
 }
 
+size_t lam_table_bytes(const PassArgs& args) {
+  size_t e = 0;
+  for (int k = 0; k < args.count; ++k) {
+    const PassDesc& v = args.u[k];
+    e += size_t(v.lam_ndim == 3 ? v.n1 + v.A / v.n1 : v.A) + size_t(v.n);
+  }
+  return e * sizeof(double);
+}
+
 size_t plain_bytes(int n, int prec) {
   if (prec == 6) return 0;  // the FP8 class has pipelined images only
   const size_t per = size_t(n) * n * elem_bytes(prec);
