@@ -222,6 +222,9 @@ def main():
     for pc in pcs.values():
         pc.close()
     del zo_all
+    pressure = None
+    if not args.only:
+        pressure = bench_pressure_route(args, [p for p in ("f64", "f32") if p in precisions])
     small = None
     if args.small and not args.only:
         small = bench_small(args, [p for p in args.small.split(",") if p])
@@ -243,7 +246,7 @@ def main():
            "rel_err_vs_oracle": (head["errors"] or {}).get("rel_err_max"),
            "rel_maxnorm_err_vs_oracle": (head["errors"] or {}).get("rel_maxnorm_err_max"),
            "plan_setup_s": round(setup_s, 3), "roofline": roofline, "cpu_baseline": cpu,
-           "ladder": ladder, "small_2d_16_p2": small, "batch_256_patches": batch, "serving": serving}
+           "ladder": ladder, "pressure_route_67cube": pressure, "small_2d_16_p2": small, "batch_256_patches": batch, "serving": serving}
     print(json.dumps(out))
 
 
@@ -310,6 +313,52 @@ def cpu_model():
     except OSError:
         pass
     return None
+
+
+def bench_pressure_route(args, precisions):
+    """The 67^3 pressure block of the 64^3 p = 3 patch, 16 residuals: FD form (Lambda = I) vs banded solves.
+
+    The FD form runs five mode products per apply on the MFMA kernels; the
+    banded route (Sec. 5.2) one banded Cholesky solve per mode. Milliseconds
+    per 16-residual apply (HIP events on the launch stream), and the relative
+    difference of the two results.
+    """
+    import torch
+
+    from oracle.assemble import pressure_1d
+    from paper_1712_00403_amd import fd, workloads
+    Ms = [pressure_1d(64, 3)] * 3
+    out = {}
+    for prec in precisions:
+        plans = {"fd_form": fd.Plan(None, Ms, precision=prec), "banded": fd.Plan(None, Ms, precision=prec, banded=True)}
+        dt = torch.float64 if prec == "f64" else torch.float32
+        N = plans["banded"].N
+        r = torch.from_numpy(workloads.residuals(5, 16, N)).to(dt).cuda()
+        res, zs = {}, {}
+        for name, plan in plans.items():
+            z = torch.empty_like(r)
+            for _ in range(args.warmup):
+                plan.apply(r, z)
+            torch.cuda.synchronize()
+            fd.timing_enable(True)
+            for _ in range(args.steps):
+                plan.apply(r, z)
+            stages = fd.timing_read()
+            fd.timing_enable(False)
+            ms = sum(v[0] for v in stages.values()) / args.steps
+            res[name] = {"ms_per_apply": round(ms, 4),
+                         "all_passes_gb_per_s": 16 * N * 2 * r.element_size() * (5 if name == "fd_form" else 3)
+                         / (ms * 1e-3) / 1e9}
+            zs[name] = z
+        d = (zs["banded"] - zs["fd_form"]).double()
+        res["rel_diff"] = float(d.norm() / zs["fd_form"].double().norm())
+        res["speedup_banded"] = res["fd_form"]["ms_per_apply"] / res["banded"]["ms_per_apply"]
+        out[prec] = res
+        log(f"pressure 67^3 x 16 {prec}: FD form {res['fd_form']['ms_per_apply']:.3f} ms, banded "
+            f"{res['banded']['ms_per_apply']:.3f} ms, rel diff {res['rel_diff']:.1e}")
+        for plan in plans.values():
+            plan.close()
+    return out
 
 
 def bench_small(args, precisions):

@@ -121,6 +121,19 @@ fd_status fd_assemble_1d(int32_t n_el, int32_t degree, int32_t regularity, int32
 fd_status fd_nitsche_stiffness_1d(int32_t n_el, int32_t degree, int32_t regularity, double c_pen, int32_t* n_out,
                                   double* K);
 
+/* Mixed univariate integrals over all functions of two spline spaces on the
+ * uniform mesh of fd_assemble_1d: X[l][m] = int b_{a,l}^(da) b_{b,m}^(db),
+ * da, db in {0, 1} (value or first derivative), space a of (deg_a, reg_a),
+ * space b of (deg_b, reg_b), no function dropped. These are the factors of
+ * the Stokes blocks that the preconditioner does not hold (Sec. 3: the
+ * off-diagonal velocity blocks A_rs and the divergence blocks B_r of the
+ * cube). Quadrature: npts Gauss points per element (npts <= 0 selects
+ * max(deg_a, deg_b) + 2, exact for these products). *ma, *mb receive the
+ * space dimensions; X (host, ma*mb column-major) may be NULL to query them.
+ * Errors: FD_E_ARG. Host computation only. */
+fd_status fd_mixed_1d(int32_t n_el, int32_t deg_a, int32_t reg_a, int32_t da, int32_t deg_b, int32_t reg_b,
+                      int32_t db, int32_t npts, int32_t* ma, int32_t* mb, double* X);
+
 /* Gauss-Legendre points and weights on the element mesh used by
  * fd_assemble_1d: x, w host arrays of n_el*npts (element-major). */
 fd_status fd_quadrature_1d(int32_t n_el, int32_t npts, double* x, double* w);

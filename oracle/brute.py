@@ -167,3 +167,44 @@ def rt_velocity_block_variational(n_el, p, k, c_pen):
             cons = 2.0 * (np.einsum("iq,jq,q->ij", Sn, Vf, Wf) + np.einsum("jq,iq,q->ij", Sn, Vf, Wf))
             P += pen - cons
     return P
+
+
+def stokes_variational_cube(n_el, p):
+    """The TH Stokes blocks on the unit cube with G = id, nu = 1 from their forms (Sec. 3), tiny grids only.
+
+    [A_rs]_ij = a(e_r B_i, e_s B_j) = int 2 grad^s(e_r B_i) : grad^s(e_s B_j)
+    and [B_r]_lj = b(e_r B_j, Q_l) = -int Q_l div(e_r B_j), over ALL velocity
+    functions (degree p+1, regularity p-1) and pressure functions (degree p,
+    regularity p-1), i_1 fastest, by tensor Gauss quadrature with every
+    symmetric gradient formed as a 3 x 3 matrix at each point. Independent of
+    the Kronecker factorisation it checks. Returns (A as a dict (r, s) ->
+    matrix, B as a list over r).
+    """
+    from .bspline import basis_derivatives, basis_values, element_quadrature, open_uniform_knots
+
+    xq, wq = element_quadrature(n_el, p + 3)
+    x, w = xq.ravel(), wq.ravel()
+    kv = open_uniform_knots(n_el, p + 1, p - 1)
+    kq = open_uniform_knots(n_el, p, p - 1)
+    V, dV = basis_values(kv, p + 1, x), basis_derivatives(kv, p + 1, x)
+    Q = basis_values(kq, p, x)
+
+    def kron3(t1, t2, t3):
+        return np.kron(t3, np.kron(t2, t1))   # rows: functions i_1 fastest, columns: points q_1 fastest
+
+    W = kron3(w[None, :], w[None, :], w[None, :]).ravel()
+    G = np.stack([kron3(dV, V, V), kron3(V, dV, V), kron3(V, V, dV)], axis=2)   # (nfun, npt, 3)
+    QQ = kron3(Q, Q, Q)
+    nf, npt = G.shape[:2]
+
+    def symgrad(r):
+        S = np.zeros((nf, npt, 3, 3))
+        S[:, :, r, :] += 0.5 * G
+        S[:, :, :, r] += 0.5 * G
+        return S
+
+    Ss = [symgrad(r) for r in range(3)]
+    A = {(r, s): 2.0 * np.einsum("iqab,jqab,q->ij", Ss[r], Ss[s], W) for r in range(3) for s in range(3)}
+    # div(e_r B_j) = d_r B_j
+    Bl = [-(QQ * W[None, :]) @ G[:, :, r].T for r in range(3)]
+    return A, Bl

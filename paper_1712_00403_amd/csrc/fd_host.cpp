@@ -277,6 +277,35 @@ int band_cholesky(int n, const double* M, int max_band, int* b_out, double* band
   return 0;
 }
 
+// Mixed univariate integrals X[l][m] = int b_{a,l}^(da) b_{b,m}^(db) over all
+// functions of two spline spaces on the same uniform mesh (da, db in {0, 1}:
+// value or first derivative), by Gauss quadrature with npts points per
+// element; X is ma x mb column-major. The blocks of the Stokes system that
+// couple different spaces or a derivative with a value (Sec. 3) are Kronecker
+// products of these. 0, or 1 on bad arguments.
+int mixed_1d(int n_el, int deg_a, int reg_a, int da, int deg_b, int reg_b, int db, int npts, int* ma, int* mb,
+             double* X) {
+  if ((da != 0 && da != 1) || (db != 0 && db != 1)) return 1;
+  std::vector<double> Ba, dBa, Bb, dBb;
+  std::vector<int> la, ha, lb, hb;
+  if (basis_tables(n_el, deg_a, reg_a, 0, npts, ma, Ba, dBa, la, ha) != 0) return 1;
+  if (basis_tables(n_el, deg_b, reg_b, 0, npts, mb, Bb, dBb, lb, hb) != 0) return 1;
+  if (!X) return 0;
+  const int nq = n_el * npts;
+  std::vector<double> xq(nq), wq(nq);
+  element_quadrature(n_el, npts, xq.data(), wq.data());
+  const std::vector<double>& Ta = da ? dBa : Ba;
+  const std::vector<double>& Tb = db ? dBb : Bb;
+  for (int m = 0; m < *mb; ++m)
+    for (int l = 0; l < *ma; ++l) {
+      double s = 0.0;
+      const int q0 = std::max(la[l], lb[m]), q1 = std::min(ha[l], hb[m]);
+      for (int q = q0; q < q1; ++q) s += wq[q] * Ta[size_t(l) * nq + q] * Tb[size_t(m) * nq + q];
+      X[l + size_t(*ma) * m] = s;
+    }
+  return 0;
+}
+
 // ------------------------------------------------------------------ eigensolve
 
 // Symmetric eigenproblem by cyclic Jacobi (row-cyclic ordering), with the

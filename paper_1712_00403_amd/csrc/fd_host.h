@@ -24,6 +24,11 @@ int assemble_1d(int n_el, int degree, int regularity, int dirichlet, int npts, c
 // be null to query m.
 int nitsche_stiffness_1d(int n_el, int degree, int regularity, double c_pen, int* m_out, double* K);
 
+// Mixed univariate integrals int b_a^(da) b_b^(db) over all functions of two
+// spaces (X: ma x mb column-major; null to query the sizes). 0, or 1.
+int mixed_1d(int n_el, int deg_a, int reg_a, int da, int deg_b, int reg_b, int db, int npts, int* ma, int* mb,
+             double* X);
+
 // Banded Cholesky M = L L^T of an SPD matrix of bandwidth b <= max_band:
 // band[j*n + i] = L(i, i-j) (j = 1..b; row j = 0 unused), rdiag[i] = 1/L(i,i).
 // band/rdiag may be null to query b. 0, 1 (arguments, asymmetry, b too

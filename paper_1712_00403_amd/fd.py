@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "FD_OK", 1: "FD_E_ARG", 2: "FD_E_NOTSPD", 3: "FD_E_NOMEM", 4:
                 5: "FD_E_UNSUPPORTED"}
 
 # every symbol declared in include/fd.h
-EXPORTS = ("fd_assemble_1d", "fd_nitsche_stiffness_1d", "fd_quadrature_1d", "fd_factor_1d", "fd_geometry_coefficients",
+EXPORTS = ("fd_assemble_1d", "fd_nitsche_stiffness_1d", "fd_mixed_1d", "fd_quadrature_1d", "fd_factor_1d", "fd_geometry_coefficients",
            "fd_separable_factors", "fd_operator_diagonal", "fd_setup", "fd_setup_mass_banded", "fd_destroy",
            "fd_plan_size", "fd_plan_device_bytes", "fd_workspace_bytes", "fd_plan_factors", "fd_apply",
            "fd_apply_batched", "fd_batch_create", "fd_batch_apply", "fd_batch_tune", "fd_batch_set_config",
@@ -59,6 +59,7 @@ def lib():
     L.fd_last_error.restype = ctypes.c_char_p
     L.fd_assemble_1d.argtypes = [ctypes.c_int32] * 5 + [c_dp, c_dp, ctypes.POINTER(ctypes.c_int32), c_dp, c_dp]
     L.fd_quadrature_1d.argtypes = [ctypes.c_int32, ctypes.c_int32, c_dp, c_dp]
+    L.fd_mixed_1d.argtypes = [ctypes.c_int32] * 8 + [ctypes.POINTER(ctypes.c_int32)] * 2 + [c_dp]
     L.fd_nitsche_stiffness_1d.argtypes = [ctypes.c_int32] * 3 + [ctypes.c_double, ctypes.POINTER(ctypes.c_int32),
                                                                   c_dp]
     L.fd_factor_1d.argtypes = [ctypes.c_int32, c_dp, c_dp, c_dp, c_dp]
@@ -100,9 +101,10 @@ def lib():
     L.fd_timing_read.argtypes = [c_dp, ctypes.POINTER(ctypes.c_int32)]
     L.fd_timing_launches.argtypes = [ctypes.c_int32, ctypes.POINTER(FDLaunchTime), ctypes.POINTER(ctypes.c_int32)]
     L.fd_timing_launches.restype = ctypes.c_int
-    for name in ("fd_timing_enable", "fd_timing_read", "fd_assemble_1d", "fd_nitsche_stiffness_1d", "fd_quadrature_1d", "fd_factor_1d",
-                 "fd_geometry_coefficients", "fd_separable_factors", "fd_operator_diagonal", "fd_setup", "fd_setup_mass_banded", "fd_destroy",
-                 "fd_plan_factors", "fd_apply", "fd_apply_batched"):
+    for name in ("fd_timing_enable", "fd_timing_read", "fd_assemble_1d", "fd_nitsche_stiffness_1d", "fd_mixed_1d",
+                 "fd_quadrature_1d", "fd_factor_1d", "fd_geometry_coefficients", "fd_separable_factors",
+                 "fd_operator_diagonal", "fd_setup", "fd_setup_mass_banded", "fd_destroy", "fd_plan_factors", "fd_apply",
+                 "fd_apply_batched"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -148,6 +150,17 @@ def nitsche_stiffness_1d(n_el, degree, regularity, c_pen):
     _check(L.fd_nitsche_stiffness_1d(n_el, degree, regularity, float(c_pen), ctypes.byref(m),
                                      K.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     return np.ascontiguousarray(K)
+
+
+def mixed_1d(n_el, deg_a, reg_a, da, deg_b, reg_b, db, npts=0):
+    """X[l, m] = int b_{a,l}^(da) b_{b,m}^(db) over all functions of two spaces (fd_mixed_1d)."""
+    L = lib()
+    ma, mb = ctypes.c_int32(0), ctypes.c_int32(0)
+    args = (n_el, deg_a, reg_a, da, deg_b, reg_b, db, npts)
+    _check(L.fd_mixed_1d(*args, ctypes.byref(ma), ctypes.byref(mb), None))
+    X = np.zeros((ma.value, mb.value), order="F")
+    _check(L.fd_mixed_1d(*args, ctypes.byref(ma), ctypes.byref(mb), X.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return np.ascontiguousarray(X)
 
 
 def quadrature_1d(n_el, npts):

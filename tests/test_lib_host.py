@@ -137,3 +137,20 @@ def test_raviart_thomas_sizes_from_library(fd):
         assert [K.shape[0] for K in Ks] == [M.shape[0] for M in Ms]
     _, Mp = block_factors(prob.blocks[3])
     assert [M.shape[0] for M in Mp] == [8, 10, 9]
+
+
+@pytest.mark.parametrize("n_el,p", [(3, 2), (5, 3), (2, 5)])
+def test_mixed_integrals_match_oracle(fd, n_el, p):
+    """fd_mixed_1d: the Stokes cube's univariate factors against the oracle's (velocity derivative x value,
+    pressure x velocity derivative, pressure x velocity)."""
+    from oracle.stokes import univariate
+    f = univariate(n_el, p)
+    C = fd.mixed_1d(n_el, p + 1, p - 1, 1, p + 1, p - 1, 0)
+    D = fd.mixed_1d(n_el, p, p - 1, 0, p + 1, p - 1, 1)
+    N = fd.mixed_1d(n_el, p, p - 1, 0, p + 1, p - 1, 0)
+    for X, name in ((C, "CV"), (D, "DQ"), (N, "NQ")):
+        np.testing.assert_allclose(X, f[name], rtol=0, atol=1e-13 * np.abs(f[name]).max())
+    K, M = fd.assemble_1d(n_el, p + 1, p - 1, False)
+    np.testing.assert_allclose(fd.mixed_1d(n_el, p + 1, p - 1, 1, p + 1, p - 1, 1), K, rtol=0, atol=1e-12)
+    with pytest.raises(fd.FDError):
+        fd.mixed_1d(n_el, p, p - 1, 2, p, p - 1, 0)
