@@ -47,6 +47,8 @@ extern template hipError_t launch3_p<0>(const PassArgs&, int, int, size_t, hipSt
 extern template hipError_t launch3_p<1>(const PassArgs&, int, int, size_t, hipStream_t);
 extern template hipError_t launch3_p<2>(const PassArgs&, int, int, size_t, hipStream_t);
 extern template hipError_t launch3_p<3>(const PassArgs&, int, int, size_t, hipStream_t);
+extern template hipError_t launch3_p<4>(const PassArgs&, int, int, size_t, hipStream_t);
+extern template hipError_t launch3_p<5>(const PassArgs&, int, int, size_t, hipStream_t);
 extern template hipError_t launch3_p<6>(const PassArgs&, int, int, size_t, hipStream_t);
 
 int v2_max_mt_of(int prec) { return prec == 0 ? v2_max_mt<0>() : prec == 1 ? v2_max_mt<1>() : v2_max_mt<2>(); }
@@ -70,6 +72,8 @@ bool v3_plan(int prec, int mode, int max_n, int mt, int* chunk, size_t* smem) {
   if (prec == 1) return v3_plan_p<1>(mode, max_n, mt, chunk, smem);
   if (prec == 2) return v3_plan_p<2>(mode, max_n, v3_mt(prec, mt), chunk, smem);
   if (prec == 3) return v3_plan_p<3>(mode, max_n, v3_mt(prec, mt), chunk, smem);
+  if (prec == 4) return v3_plan_p<4>(mode, max_n, v3_mt(prec, mt), chunk, smem);
+  if (prec == 5) return v3_plan_p<5>(mode, max_n, v3_mt(prec, mt), chunk, smem);
   if (prec == 6) return v3_plan_p<6>(mode, max_n, v3_mt(prec, mt), chunk, smem);
   return false;
 }
@@ -80,6 +84,8 @@ hipError_t launch_pass3(const PassArgs& args, int prec, int mode, int mt, size_t
   if (prec == 1) return launch3_p<1>(args, mode, mt, smem, stream);
   if (prec == 2) return launch3_p<2>(args, mode, v3_mt(prec, mt), smem, stream);
   if (prec == 3) return launch3_p<3>(args, mode, v3_mt(prec, mt), smem, stream);
+  if (prec == 4) return launch3_p<4>(args, mode, v3_mt(prec, mt), smem, stream);
+  if (prec == 5) return launch3_p<5>(args, mode, v3_mt(prec, mt), smem, stream);
   if (prec == 6) return launch3_p<6>(args, mode, v3_mt(prec, mt), smem, stream);
   return hipErrorInvalidValue;
 }
@@ -233,9 +239,10 @@ int v3_ld(int n, int prec) {
 }
 
 size_t v3_factor_bytes(int n, int prec) {
-  if (prec < 0 || (prec > 3 && prec != 6)) return 0;
+  if (prec < 0 || prec > 6) return 0;
   const size_t eb = prec == 0 ? 8 : (prec == 1 ? 4 : 2);
-  return size_t(v3_ld(n, prec)) * v3_ld(n, prec) * eb;
+  const size_t planes = (prec == 4 || prec == 5) ? 2 : 1;  // split classes: hi plane, then lo plane
+  return planes * size_t(v3_ld(n, prec)) * v3_ld(n, prec) * eb;
 }
 
 void v3_factor(int n, const double* F, int prec, bool second, void* dst) {
@@ -258,10 +265,20 @@ void v3_factor(int n, const double* F, int prec, bool second, void* dst) {
       if (prec == 1) pos ^= 2 * rhalf(r);
       const double v = F[r + size_t(n) * c];
       const size_t idx = size_t(r) * ld + pos;
-      if (prec == 0) reinterpret_cast<double*>(dst)[idx] = v;
-      else if (prec == 1) reinterpret_cast<float*>(dst)[idx] = float(v);
-      else if (prec == 2) reinterpret_cast<uint16_t*>(dst)[idx] = to_bf16(float(v));
-      else reinterpret_cast<_Float16*>(dst)[idx] = (_Float16)float(v);
+      const size_t lo = size_t(ld) * ld;  // the lo plane of the split classes
+      if (prec == 0) {
+        reinterpret_cast<double*>(dst)[idx] = v;
+      } else if (prec == 1) {
+        reinterpret_cast<float*>(dst)[idx] = float(v);
+      } else if (prec == 2 || prec == 4) {
+        const uint16_t h = to_bf16(float(v));
+        reinterpret_cast<uint16_t*>(dst)[idx] = h;
+        if (prec == 4) reinterpret_cast<uint16_t*>(dst)[lo + idx] = to_bf16(float(v - double(from_bf16(h))));
+      } else {
+        const _Float16 h = (_Float16)float(v);
+        reinterpret_cast<_Float16*>(dst)[idx] = h;
+        if (prec == 5) reinterpret_cast<_Float16*>(dst)[lo + idx] = (_Float16)float(v - double((float)h));
+      }
     }
 }
 

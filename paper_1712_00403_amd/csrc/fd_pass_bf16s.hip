@@ -1,8 +1,10 @@
 // Pass kernels instantiated for precision class 4 (bf16s).
 #include "fd_pass.inc"
 #include "fd_pass2.inc"
+#include "fd_pass3.inc"
 
 namespace fdk {
 template hipError_t launch_p<4>(const PassArgs&, int, hipStream_t);
 template hipError_t launch2_p<4>(const PassArgs&, int, int, size_t, hipStream_t);
+template hipError_t launch3_p<4>(const PassArgs&, int, int, size_t, hipStream_t);
 }  // namespace fdk

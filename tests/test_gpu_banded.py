@@ -125,3 +125,27 @@ def test_banded_plans_are_refused_where_unsupported():
     bad = np.array([[1.0, 2.0], [2.0, 1.0]])
     with pytest.raises(fd.FDError, match="FD_E_NOTSPD"):
         fd.Plan(None, [bad, bad], precision="f64", banded=True)
+
+
+def _banded_spd(n, bw):
+    """A well-conditioned SPD matrix of bandwidth bw (diagonally dominant)."""
+    i = np.arange(n)
+    D = np.abs(i[:, None] - i[None, :])
+    M = np.where(D <= bw, 1.0 / (1.0 + D), 0.0)
+    M[i, i] = 2.0 * bw + 1.0
+    return M
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_banded_wide_bands_use_the_staged_kernel(prec):
+    """Bandwidths above 8 take the LDS-staged sweep in every mode; 8 and below the register one."""
+    _case(f"banded route with bandwidths 9..11 and 1..8, prec={prec}")
+    from paper_1712_00403_amd import fd
+    for bws in ((10, 9, 11), (8, 1, 7)):
+        Ms = [_banded_spd(n, bw) for n, bw in zip((14, 12, 17), bws)]
+        plan = fd.Plan(None, Ms, precision=prec, banded=True)
+        r = workloads.residuals(98, 2, plan.N)
+        z = _run(plan, r)
+        for j in range(2):
+            check_close(z[j], mass_solve_banded(Ms, r[j]), prec, f"bandwidths {bws} residual {j}")
+        plan.close()

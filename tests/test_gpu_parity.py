@@ -377,7 +377,7 @@ def _spd_pair(n, rng):
     return K, M
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f16", "fp8_split"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f16", "bf16_split", "f16_split", "fp8_split"])
 @pytest.mark.parametrize("shape", _random_cases(2024, 8))
 def test_random_orders(prec, shape):
     _case(f"random-order block n={shape} prec={prec}")
