@@ -17,7 +17,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = ["fd_api.hip", "fd_kernels.hip", "fd_host.cpp", "fd_geometry.cpp", "fd_pass_f64.hip", "fd_pass_f32.hip",
            "fd_pass_bf16.hip", "fd_pass_f16.hip", "fd_pass_bf16s.hip", "fd_pass_f16s.hip", "fd_pass_fp8s.hip",
            "fd_batch_f64.hip", "fd_batch_f32.hip", "fd_batch_bf16.hip", "fd_batch_f16.hip",
-           "fd_batch_bf16s.hip", "fd_batch_f16s.hip", "fd_banded.hip"]
+           "fd_batch_bf16s.hip", "fd_batch_f16s.hip", "fd_banded.hip", "fd_slab.hip"]
 
 COMMON = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
           # packed FP32 VALU ops are kept out of every kernel

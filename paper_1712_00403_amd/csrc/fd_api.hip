@@ -42,6 +42,12 @@ struct fd_plan_s {
   int MT[3] = {0, 0, 0}, KS[3] = {0, 0, 0};
   int device = 0;
   int family_cap = 3;  // most capable kernel family the plan's passes may use
+  // slab route (3D BF16/FP16, n1, n2 <= 144): stage 0 and 4 are slab passes
+  // over both in-plane modes and the tensor stays in the 16-bit layout of z
+  // until the last one; stages 1 and 3 are empty. xs_sb: FP16 scale of the
+  // backward slab pass's intermediate (after the last and first modes).
+  bool slab = false;
+  float xs_sb = 1.0f;
   // banded route of a mass-only block (fd_setup_mass_banded): per direction
   // the band of the Cholesky factor of M_i on the device
   bool banded = false;
@@ -111,9 +117,13 @@ bool io_is_f64(int prec) { return prec == FD_F64; }
 // 2D: stage 0 mode-1 forward, 2 mode-2 fused, 4 mode-1 backward.
 constexpr int kStages = 5;
 
-bool unit_pass(const fd_plan_s* p, const fd_work& wk, int stage, fdk::PassDesc& u) {
+// `slab_route`: false for callers that run every plan on the five-stage
+// schedule (the persistent batch).
+bool unit_pass(const fd_plan_s* p, const fd_work& wk, int stage, fdk::PassDesc& u, bool slab_route = true) {
   std::memset(&u, 0, sizeof(u));
   if (p->banded) return false;  // runs the banded solves instead (band_pass)
+  const bool slab = slab_route && p->slab;
+  if (slab && stage != 2) return false;  // slab passes (slab_pass)
   const int n1 = p->n[0], n2 = p->n[1], n3 = p->n[2];
   u.in = wk.z;
   u.out = wk.z;
@@ -163,12 +173,69 @@ bool unit_pass(const fd_plan_s* p, const fd_work& wk, int stage, fdk::PassDesc& 
   u.KS = p->KS[dir];
   u.lam_ndim = p->ndim;
   u.n1 = n1;
+  u.sA = u.A;
   for (int i = 0; i < 3; ++i) {
     u.d[i] = p->d_dev[i];
     u.w[i] = p->lam_w[i];
   }
+  if (slab) {
+    // fused last-mode pass on the 16-bit layout: z viewed as 16-bit entries
+    // from the plane offset, residuals 2 ld apart, planes 2 A apart; its FP16
+    // input is already scaled, its output carries the backward slab pass's
+    // input scale
+    const int64_t A = int64_t(n1) * n2;
+    u.in = static_cast<const char*>(wk.z) + 2 * fdk::slab_off16(A);
+    u.out = static_cast<char*>(wk.z) + 2 * fdk::slab_off16(A);
+    u.ld = 2 * wk.ld;
+    u.sA = int32_t(2 * A);
+    u.xscale = 1.0f;
+    u.oscale = p->xs[3] / (p->xs[2] * p->qs);
+  }
   return true;
 }
+
+// Effective precision class of the pass of `p` in `stage`: the fused pass of a
+// slab-route plan reads and writes 16-bit data (classes 7 and 8).
+int unit_class(const fd_plan_s* p, int stage) {
+  if (p->slab && stage == 2) return p->prec == FD_BF16 ? 7 : 8;
+  return p->prec;
+}
+
+// Slab pass of a slab-route plan: stage 0 reads r (FP32, pre-scaled by
+// D^{-1/2} if the plan has one) and writes the 16-bit layout of z; stage 4
+// reads that layout and writes FP32 z (post-scaled).
+bool slab_pass(const fd_plan_s* p, const fd_work& wk, int stage, fdk::SlabDesc& d) {
+  if (!p->slab || wk.nrhs == 0 || (stage != 0 && stage != 4)) return false;
+  std::memset(&d, 0, sizeof(d));
+  const bool fwd = stage == 0;
+  d.in = fwd ? wk.r : wk.z;
+  d.out = wk.z;
+  d.f1 = fwd ? p->v_fwd[0] : p->v_bwd[0];
+  d.f2 = fwd ? p->v_fwd[1] : p->v_bwd[1];
+  d.scale = static_cast<const float*>(p->scale_dev);
+  d.post = fwd ? 0 : 1;
+  d.ld = wk.ld;
+  d.n1 = p->n[0];
+  d.n2 = p->n[1];
+  d.n3 = p->n[2];
+  d.nrhs = wk.nrhs;
+  d.ldf1 = fdk::v3_ld(p->n[0], p->prec);
+  d.ldf2 = fdk::v3_ld(p->n[1], p->prec);
+  d.in16 = fwd ? 0 : 1;
+  d.out16 = fwd ? 1 : 0;
+  if (fwd) {
+    d.s_in = p->xs[0];
+    d.s_mid = p->xs[1] / p->xs[0];
+    d.s_out = p->xs[2] / p->xs[1];
+  } else {
+    d.s_in = 1.0f;
+    d.s_mid = p->xs_sb / p->xs[3];
+    d.s_out = 1.0f / p->xs_sb;
+  }
+  return true;
+}
+
+int slab_mt(const fd_plan_s* p) { return std::max(p->MT[0], p->MT[1]); }
 
 int stage_mode(const fdk::PassDesc& u) {
   if (u.flags & fdk::kFuseLambda) return 2;
@@ -233,8 +300,10 @@ fd_status run_work(int count, const fd_work* work, hipStream_t stream) {
       for (int i = 0; i < count; ++i) {
         fdk::PassDesc probe;
         fdk::BandArgs bprobe;
+        fdk::SlabDesc sprobe;
         if (work[i].nrhs > 0 && (unit_pass(work[i].plan, work[i], stage, probe) ||
-                                 band_pass(work[i].plan, work[i], stage, bprobe)))
+                                 band_pass(work[i].plan, work[i], stage, bprobe) ||
+                                 slab_pass(work[i].plan, work[i], stage, sprobe)))
           any = true;
       }
       if (any) {
@@ -244,13 +313,13 @@ fd_status run_work(int count, const fd_work* work, hipStream_t stream) {
         if (e != hipSuccess) return hip_fail(e, "timing event");
       }
     }
-    for (int prec = 0; prec <= 6; ++prec) {
+    for (int prec = 0; prec <= 8; ++prec) {
       // units of this stage and precision class
       std::vector<fdk::PassDesc> units, split_fwd, split_bwd;
       int mode = -1;
       for (int i = 0; i < count; ++i) {
         const fd_work& wk = work[i];
-        if (wk.nrhs == 0 || wk.plan->prec != prec) continue;
+        if (wk.nrhs == 0 || unit_class(wk.plan, stage) != prec) continue;
         fdk::PassDesc u;
         if (!unit_pass(wk.plan, wk, stage, u)) continue;
         mode = stage_mode(u);
@@ -288,6 +357,8 @@ fd_status run_work(int count, const fd_work* work, hipStream_t stream) {
           const bool post = (units[k].flags & fdk::kPostScale) != 0;
           if (kernel_family >= 3 && !pre && !post && fdk::v3_plan(prec, mode, units[k].n, units[k].MT, &c, &sm))
             group[k] = 3000 + units[k].n;
+          else if (prec >= 7)  // (16-bit data has the pipelined body only)
+            return fail(FD_E_HIP, "internal: no kernel for a 16-bit data pass");
           else if (kernel_family >= 2 && fdk::v2_plan(prec, mode, units[k].n, units[k].MT, &b, &c, &sm))
             group[k] = 2000 + b;
           else
@@ -389,6 +460,56 @@ fd_status run_work(int count, const fd_work* work, hipStream_t stream) {
         g_launch_records.push_back(lr);
       }
     }
+    // slab passes: one launch per precision, row-tile count and scaling, up
+    // to kMaxDesc works each
+    for (int prec = 2; prec <= 3; ++prec)
+      for (int mt = 1; mt <= fdk::kSlabMaxMT; ++mt)
+        for (int sc = 0; sc <= 1; ++sc) {
+        fdk::SlabArgs sa;
+        sa.count = 0;
+        sa.total_tiles = 0;
+        int max_n = 0;
+        auto flush = [&]() -> fd_status {
+          if (sa.count == 0) return FD_OK;
+          LaunchRecord lr{stage, 5, max_n, prec, nullptr, nullptr};
+          if (g_timing) {
+            hipError_t e = hipEventCreate(&lr.start);
+            if (e == hipSuccess) e = hipEventCreate(&lr.end);
+            if (e == hipSuccess) e = hipEventRecord(lr.start, stream);
+            if (e != hipSuccess) return hip_fail(e, "timing event");
+          }
+          hipError_t e = fdk::launch_slab(sa, prec, mt, stream);
+          if (e != hipSuccess) return hip_fail(e, "slab kernel launch");
+          if (g_timing) {
+            e = hipEventRecord(lr.end, stream);
+            if (e != hipSuccess) return hip_fail(e, "timing event");
+            g_launch_records.push_back(lr);
+          }
+          sa.count = 0;
+          sa.total_tiles = 0;
+          max_n = 0;
+          return FD_OK;
+        };
+        for (int i = 0; i < count; ++i) {
+          const fd_plan_s* p = work[i].plan;
+          fdk::SlabDesc d;
+          if (p->prec != prec || slab_mt(p) != mt || (p->scale_dev != nullptr) != (sc == 1) ||
+              !slab_pass(p, work[i], stage, d))
+            continue;
+          const int64_t tiles = int64_t(d.n3) * d.nrhs;
+          if (tiles > 0x7fffffffLL) return fail(FD_E_ARG, "fd_apply: too many tiles in one call");
+          if (sa.count == fdk::kMaxDesc || int64_t(sa.total_tiles) + tiles > 0x7fffffffLL) {
+            fd_status s = flush();
+            if (s != FD_OK) return s;
+          }
+          d.tile_begin = sa.total_tiles;
+          sa.u[sa.count++] = d;
+          sa.total_tiles += int32_t(tiles);
+          max_n = std::max(max_n, std::max(d.n1, d.n2));
+        }
+        fd_status s = flush();
+        if (s != FD_OK) return s;
+      }
     if (rec.start) {
       hipError_t e = hipEventRecord(rec.end, stream);
       if (e != hipSuccess) return hip_fail(e, "timing event");
@@ -407,7 +528,7 @@ fd_status run_work(int count, const fd_work* work, hipStream_t stream) {
 static bool batch_pass(int prec, const fd_work& wk, int stage, int choice, int* body, fdk::BatchDesc* out,
                        size_t* smem) {
   fdk::PassDesc u;
-  if (wk.nrhs == 0 || !unit_pass(wk.plan, wk, stage, u)) return false;
+  if (wk.nrhs == 0 || !unit_pass(wk.plan, wk, stage, u, false)) return false;
   fdk::BatchDesc bd{};
   bd.u = u;
   bd.mode = stage_mode(u);
@@ -915,7 +1036,7 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
     const int last = ndim - 1;
     // mean squares after the division (sq[0]) and after the backward products
     // along modes last, last-1 (sq[1], sq[2])
-    double sq[3] = {0.0, 0.0, 0.0};
+    double sq[3] = {0.0, 0.0, 0.0}, sq_sb = 0.0;
     {
       uint64_t st = 0x9E3779B97F4A7C15ull;
       for (int t = 0; t < 4096; ++t) {
@@ -932,8 +1053,12 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
         sq[0] += v;
         sq[1] += v * cn[last][k[last]];
         if (ndim == 3) sq[2] += v * cn[last][k[last]] * cn[1][k[1]];
+        // slab route: the backward slab pass's intermediate follows the
+        // products along the last and the first mode
+        if (ndim == 3) sq_sb += v * cn[last][k[last]] * cn[0][k[0]];
       }
       for (double& v : sq) v /= 4096.0;
+      sq_sb /= 4096.0;
     }
     const double target = fp8 ? 4.0 : 1.0;
     auto pow2 = [target](double rms) {
@@ -952,10 +1077,22 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
     if (ndim == 3) {
       p->xs[3] = pow2(r0 * std::sqrt(sq[1]));
       p->xs[4] = pow2(r0 * std::sqrt(sq[2]));
+      p->xs_sb = pow2(r0 * std::sqrt(sq_sb));
     } else {
       p->xs[4] = pow2(r0 * std::sqrt(sq[1]));
       p->xs[0] = pow2(r0);
     }
+  }
+  // Slab route of 3D BF16/FP16 plans (in-plane orders within the slab kernel,
+  // the last order within the 16-bit fused pass); FD_SLAB=0 at setup keeps
+  // the five-stage schedule (diagnostics, tests of both routes)
+  if (ndim == 3 && (p->prec == FD_BF16 || p->prec == FD_F16) && p->family_cap >= 3 &&
+      n[0] <= 16 * fdk::kSlabMaxMT && n[1] <= 16 * fdk::kSlabMaxMT) {
+    int c3 = 0;
+    size_t s3 = 0;
+    const char* senv = std::getenv("FD_SLAB");
+    p->slab = !(senv && std::strcmp(senv, "0") == 0) &&
+              fdk::v3_plan(p->prec == FD_BF16 ? 7 : 8, 2, n[2], (n[2] + 15) / 16, &c3, &s3);
   }
   // Pack U_i^T (forward) and U_i (backward) in fragment order.
   const int ks = fdk::mfma_kstep(p->prec);

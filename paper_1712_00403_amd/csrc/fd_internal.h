@@ -53,6 +53,7 @@ struct PassDesc {
   int32_t lam_ndim;     // 2 or 3: how a pencil index splits into direction indices
   int32_t n1;           // first direction size (3D fused pass: a = i1 + n1*i2)
   int32_t tiles_per_rhs;
+  int32_t sA;           // 16-bit data classes: elements between consecutive i (A otherwise)
 };
 
 // ---- one persistent launch per batched apply (fd_batch.inc)
@@ -94,6 +95,49 @@ struct PassArgs {
   int32_t lam_lds;      // pipelined divide passes: 1 = the weighted eigenvalues of every unit sit in LDS
   PassDesc u[kMaxDesc];
 };
+
+// ---- slab passes of 3D BF16/FP16 plans (fd_slab.hip)
+// One workgroup takes one i3-slab (n1 x n2 entries, contiguous) of one
+// residual and applies both in-plane products, out[j1, j2] =
+// sum_{i1, i2} F1[j1, i1] F2[j2, i2] x[i1, i2], with the slab and the
+// intermediate in LDS. Between the slab passes and the fused last-mode pass
+// the tensor lives in z as 16 bits per entry ("16-bit layout"): entry
+// (i1, i2, i3) of residual j at 16-bit index 2 j ld + off16 + 2 A i3 + i1 +
+// n1 i2 of z (A = n1 n2, off16 = A rounded down to even), i.e. in the upper
+// half of the bytes that the FP32 plane i3 of that residual occupies. A slab
+// pass therefore reads and writes inside the FP32 footprint of its own slab
+// only, which keeps z == r and the final FP32 store race-free.
+constexpr int kSlabMaxMT = 9;   // n1, n2 <= 144
+constexpr int kSlabWaves = 9;   // 3 x 3 wavefronts, each a block of output tiles
+
+struct SlabDesc {
+  const void* in;       // FP32 vectors (in16 == 0) or z in the 16-bit layout
+  void* out;            // z: FP32 (out16 == 0) or the 16-bit layout
+  const void* f1;       // padded row-major factor image of the product along i1 (ldf1 entries a row)
+  const void* f2;       // the same along i2
+  const float* scale;   // D^{-1/2} (N entries) applied on load (pre) or store (post), or null
+  int64_t ld;           // FP32 elements between residual vectors
+  int64_t tile_begin;   // first slab of this unit within the launch
+  int32_t n1, n2, n3, nrhs;
+  int32_t ldf1, ldf2;
+  int32_t in16, out16;
+  int32_t post;         // 1: scale multiplies the output, 0: the input
+  // FP16 range scaling (powers of two, 1 for BF16): input before its
+  // conversion, first product's accumulators before theirs, output
+  float s_in, s_mid, s_out;
+};
+
+struct SlabArgs {
+  int32_t count;
+  int32_t total_tiles;
+  SlabDesc u[kMaxDesc];
+};
+
+// 16-bit element offset of the 16-bit layout within each plane of A entries
+__host__ __device__ inline int64_t slab_off16(int64_t A) { return A & ~int64_t(1); }
+size_t slab_lds_bytes(int mt);
+// prec: 2 (BF16) or 3 (FP16); mt: row tiles of max(n1, n2), <= kSlabMaxMT
+hipError_t launch_slab(const SlabArgs& args, int prec, int mt, hipStream_t stream);
 
 // LDS bytes of the weighted-eigenvalue tables of a divide pass (w_0 d_0, w_1 d_1
 // and w_l d_l of every unit, FP64), placed after the pipeline ring.

@@ -50,6 +50,8 @@ extern template hipError_t launch3_p<3>(const PassArgs&, int, int, size_t, hipSt
 extern template hipError_t launch3_p<4>(const PassArgs&, int, int, size_t, hipStream_t);
 extern template hipError_t launch3_p<5>(const PassArgs&, int, int, size_t, hipStream_t);
 extern template hipError_t launch3_p<6>(const PassArgs&, int, int, size_t, hipStream_t);
+extern template hipError_t launch3_p<7>(const PassArgs&, int, int, size_t, hipStream_t);
+extern template hipError_t launch3_p<8>(const PassArgs&, int, int, size_t, hipStream_t);
 
 int v2_max_mt_of(int prec) { return prec == 0 ? v2_max_mt<0>() : prec == 1 ? v2_max_mt<1>() : v2_max_mt<2>(); }
 
@@ -75,6 +77,9 @@ bool v3_plan(int prec, int mode, int max_n, int mt, int* chunk, size_t* smem) {
   if (prec == 4) return v3_plan_p<4>(mode, max_n, v3_mt(prec, mt), chunk, smem);
   if (prec == 5) return v3_plan_p<5>(mode, max_n, v3_mt(prec, mt), chunk, smem);
   if (prec == 6) return v3_plan_p<6>(mode, max_n, v3_mt(prec, mt), chunk, smem);
+  // 16-bit data classes: the fused last-mode pass only
+  if (prec == 7 && mode == 2) return v3_plan_p<7>(mode, max_n, v3_mt(prec, mt), chunk, smem);
+  if (prec == 8 && mode == 2) return v3_plan_p<8>(mode, max_n, v3_mt(prec, mt), chunk, smem);
   return false;
 }
 
@@ -87,6 +92,8 @@ hipError_t launch_pass3(const PassArgs& args, int prec, int mode, int mt, size_t
   if (prec == 4) return launch3_p<4>(args, mode, v3_mt(prec, mt), smem, stream);
   if (prec == 5) return launch3_p<5>(args, mode, v3_mt(prec, mt), smem, stream);
   if (prec == 6) return launch3_p<6>(args, mode, v3_mt(prec, mt), smem, stream);
+  if (prec == 7) return launch3_p<7>(args, mode, v3_mt(prec, mt), smem, stream);
+  if (prec == 8) return launch3_p<8>(args, mode, v3_mt(prec, mt), smem, stream);
   return hipErrorInvalidValue;
 }
 

@@ -7,4 +7,5 @@ namespace fdk {
 template hipError_t launch_p<2>(const PassArgs&, int, hipStream_t);
 template hipError_t launch2_p<2>(const PassArgs&, int, int, size_t, hipStream_t);
 template hipError_t launch3_p<2>(const PassArgs&, int, int, size_t, hipStream_t);
+template hipError_t launch3_p<7>(const PassArgs&, int, int, size_t, hipStream_t);  // 16-bit data
 }  // namespace fdk

@@ -7,4 +7,5 @@ namespace fdk {
 template hipError_t launch_p<3>(const PassArgs&, int, hipStream_t);
 template hipError_t launch2_p<3>(const PassArgs&, int, int, size_t, hipStream_t);
 template hipError_t launch3_p<3>(const PassArgs&, int, int, size_t, hipStream_t);
+template hipError_t launch3_p<8>(const PassArgs&, int, int, size_t, hipStream_t);  // 16-bit data
 }  // namespace fdk

@@ -98,7 +98,7 @@ def test_pressure_mass_block(prec, n_el, p):
     plan.close()
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f16"])
 def test_inplace_and_strided(prec):
     _case(f"in-place and ld > N, prec={prec}")
     Ks, Ms = _vel_factors((9, 6, 11), 2)
@@ -112,7 +112,7 @@ def test_inplace_and_strided(prec):
     plan.close()
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f16"])
 def test_scaled_variant(prec):
     _case(f"diagonal scaling, prec={prec}")
     Ks, Ms = _vel_factors((5, 7, 6), 3)
