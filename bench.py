@@ -30,10 +30,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "FD applies/s & DOF/s, 3D p=3 64^3 elem; mixed vs FP64 at rel-err; p50/p99 latency"
-# sources the dominant kernel is built from: HBM traffic counters recorded in
-# profiles/ count only while these files are unchanged
-KERNEL_SOURCES = ["fd_pass3.inc", "fd_pass2.inc", "fd_pass.inc", "fd_internal.h", "fd_pass_f64.hip", "fd_pass_f32.hip",
-                  "fd_api.hip", "fd_kernels.hip"]
+# HBM traffic counters recorded in profiles/ count only while the library's
+# sources (kernels, launch shapes, factor images) are unchanged
+KERNEL_SOURCES = sorted(f for f in os.listdir(os.path.join(ROOT, "paper_1712_00403_amd", "csrc"))
+                        if f.endswith((".hip", ".inc", ".h", ".cpp")))
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fd_pass3_fused_64cube_p3_traffic.json")
 PEAKS = {"f64": 78.6e12, "f32": 157.3e12, "bf16": 2.5e15, "bf16_split": 2.5e15, "f16": 2.5e15,
          "f16_split": 2.5e15, "fp8_split": 5.0e15}
@@ -99,6 +99,9 @@ def main():
     ap.add_argument("--serve-only", action="store_true")
     ap.add_argument("--small", default="f64,f32,bf16,f16,bf16_split,f16_split,fp8_split",
                     help="precisions of the 2D 16x16 legs ('' to skip)")
+    ap.add_argument("--hbm-copy-gib", type=float, default=0.0,
+                    help="first fill and copy a device buffer of this size (counter runs: the copy's FETCH_SIZE and "
+                         "WRITE_SIZE readings give the bytes-per-KiB factors of the HBM traffic figures)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -111,8 +114,17 @@ def main():
     from paper_1712_00403_amd import fd, workloads
     from paper_1712_00403_amd.precond import BlockPreconditioner
 
+    torch.cuda.set_device(0)
+    if args.hbm_copy_gib > 0:
+        n = int(args.hbm_copy_gib * (1 << 30)) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        torch.cuda.empty_cache()
     if args.batch_only:
-        torch.cuda.set_device(0)
         print(json.dumps({"batch_256_patches": bench_batch(args, [p for p in args.batch.split(",") if p])}))
         return
     if args.serve_only:
@@ -218,7 +230,8 @@ def main():
                      "speedup_vs_f64": (v["applies_per_s"] / results["f64"]["applies_per_s"]
                                         if "f64" in results else None),
                      "stage_ms": {k: round(x, 4) for k, x in v["stage_ms"].items()},
-                     "dominant_kernel_ms": round(v["dominant_ms"], 4)}
+                     "dominant_kernel_ms": round(v["dominant_ms"], 4),
+                     "dominant_kernel_hbm_bytes_counted": recorded_traffic(p)}
     for pc in pcs.values():
         pc.close()
     del zo_all
@@ -414,7 +427,10 @@ def bench_small(args, precisions):
 
 
 def bench_batch(args, precisions):
-    """256 heterogeneous 3D patches (coefficient-aware blocks) in one persistent launch per apply.
+    """256 heterogeneous 3D patches (coefficient-aware blocks) as one fixed batch (fd_batch).
+
+    The batch is tuned (persistent body choices per stage, and for BF16/FP16
+    the staged route) and the chosen route is timed.
 
     Patches: n_el per direction uniform in [8, 48], p uniform in {2..5}
     (workloads.batch_patches, seed 3); geometry G(eta)_j = eta_j + 0.1 sin(pi
@@ -500,10 +516,14 @@ def bench_batch(args, precisions):
                                    "algorithmic_gb_per_s": alg_bytes / (ms * 1e-3) / 1e9,
                                    "hbm_frac_of_peak": alg_bytes / (ms * 1e-3) / HBM_PEAK,
                                    "five_pass_gb_per_s": pass_bytes / (ms * 1e-3) / 1e9,
+                                   "hbm_bytes_per_apply_counted": recorded_traffic(f"batch_{prec}"),
                                    "ms_per_apply_grouped_launches": round(ms_grouped, 4),
-                                   "launches_per_apply": 1, "tiles": info["tiles"], "grid": info["grid"],
+                                   "route": ("staged: one launch per stage and row-tile group (slab passes, "
+                                             "16-bit fused pass)" if config == fd.Batch.STAGED else
+                                             "persistent: one launch, grid barriers between stages"),
+                                   "tiles": info["tiles"], "grid": info["grid"],
                                    "tuned_config": config, "dofs": dofs, "blocks": passes}
-        log(f"batch {prec}: {ms:.3f} ms/apply (one launch; grouped launches {ms_grouped:.3f} ms), "
+        log(f"batch {prec}: {ms:.3f} ms/apply (config {config}; grouped launches {ms_grouped:.3f} ms), "
             f"{dofs / (ms * 1e-3) / 1e9:.2f} GDOF/s, {alg_bytes / (ms * 1e-3) / 1e9:.0f} GB/s algorithmic")
         # oracle values at sampled pencils of the 8 largest and 8 drawn patches
         # (computed by tests/golden/make_batch_golden.py from the oracle alone)

@@ -7,6 +7,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
+#include <map>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -80,6 +82,24 @@ struct fd_batch_s {
   uint32_t arrivals = 0;  // barrier arrivals counted so far
   int cus = 0;
   bool tuned = false;
+  // Staged route (configuration word kBatchStaged; batches whose works are
+  // all slab-route plans, 3D BF16/FP16): one launch per stage and row-tile
+  // group instead of the persistent launch, the slab passes of stages 0 and
+  // 4 and the 16-bit fused pass of stage 2 reading their units from device
+  // tables, so the tensor crosses HBM three times in 16 bits between passes.
+  struct StagedLaunch {
+    int stage;        // 0, 2 or 4
+    int mt;           // slab: row tiles of max(n1, n2); fused: of the last order
+    bool sc;          // slab: the units scale by D^{-1/2}
+    size_t off;       // byte offset of the units (SlabDesc or BatchDesc) in sdev
+    int count;        // units
+    int64_t tiles;
+    size_t smem;      // fused: LDS bytes
+    int max_n;
+  };
+  std::vector<StagedLaunch> staged;
+  void* sdev = nullptr;
+  bool use_staged = false;
 };
 
 namespace {
@@ -645,7 +665,10 @@ static fd_status batch_upload(fd_batch_s* b) {
   return FD_OK;
 }
 
+static fd_status batch_launch_staged(fd_batch_s* b, hipStream_t stream);
+
 static fd_status batch_launch(fd_batch_s* b, hipStream_t stream) {
+  if (b->use_staged) return batch_launch_staged(b, stream);
   if (b->max_tiles == 0) return FD_OK;
   // one 8-wavefront workgroup per CU: the pass bodies are called functions
   // with a stack, and the scratch the runtime grants is sized for that
@@ -694,11 +717,159 @@ static fd_status batch_validate(int32_t count, const fd_work* work, const char* 
   return FD_OK;
 }
 
+// Configuration word of the staged route (beyond the ten bits of the
+// persistent body choices).
+constexpr int kBatchStaged = 1 << 10;
+
 // two bits per stage: the body choice of stage s in bits 2s, 2s + 1
 static int batch_config(const fd_batch_s* b) {
+  if (b->use_staged) return kBatchStaged;
   int c = 0;
   for (int st = 0; st < kStages; ++st) c |= b->width[st] << (2 * st);
   return c;
+}
+
+// Lays out and uploads the staged route when every work with residuals is a
+// slab-route plan; otherwise leaves it empty (not available).
+static fd_status batch_build_staged(fd_batch_s* b) {
+  b->staged.clear();
+  if (b->prec != FD_BF16 && b->prec != FD_F16) return FD_OK;
+  bool any = false;
+  for (const fd_work& wk : b->works) {
+    if (wk.nrhs == 0) continue;
+    if (!wk.plan->slab) return FD_OK;
+    any = true;
+  }
+  if (!any) return FD_OK;
+  const int cls = b->prec == FD_BF16 ? 7 : 8;
+  std::vector<unsigned char> image;
+  auto put = [&](const void* src, size_t bytes) {
+    const size_t off = (image.size() + 255) & ~size_t(255);
+    image.resize(off + bytes);
+    std::memcpy(image.data() + off, src, bytes);
+    return off;
+  };
+  for (int stage = 0; stage < kStages; stage += 2) {
+    if (stage == 2) {
+      // fused passes grouped by the (even) row-tile count of the last order
+      std::map<int, std::vector<fdk::BatchDesc>, std::greater<int>> groups;
+      std::map<int, std::pair<size_t, int>> plan_of;  // group -> (LDS bytes, largest order)
+      for (const fd_work& wk : b->works) {
+        fdk::PassDesc u;
+        if (wk.nrhs == 0 || !unit_pass(wk.plan, wk, 2, u)) continue;
+        int chunk = 0;
+        size_t sm = 0;
+        const int mt = (u.MT + 1) / 2 * 2;
+        if (!fdk::v3_plan(cls, 2, u.n, mt, &chunk, &sm)) return fail(FD_E_HIP, "internal: no 16-bit fused pass");
+        u.tiles_per_rhs = int32_t((int64_t(u.A) * u.B + chunk - 1) / chunk);
+        fdk::BatchDesc bd{};
+        bd.u = u;
+        bd.mode = 2;
+        bd.mt = mt;
+        bd.scale = 0;
+        groups[mt].push_back(bd);
+        auto& pl = plan_of[mt];
+        pl.first = sm;
+        pl.second = std::max(pl.second, u.n);
+      }
+      for (auto& [mt, D] : groups) {
+        int64_t t = 0;
+        for (auto& bd : D) {
+          bd.u.tile_begin = t;
+          t += int64_t(bd.u.tiles_per_rhs) * bd.u.nrhs;
+        }
+        if (t > 0x7fffffffLL) return fail(FD_E_ARG, "fd_batch_create: too many tiles in one launch");
+        fd_batch_s::StagedLaunch L{2, mt, false, put(D.data(), D.size() * sizeof(fdk::BatchDesc)), int(D.size()),
+                                   t, plan_of[mt].first, plan_of[mt].second};
+        b->staged.push_back(L);
+      }
+    } else {
+      // slab passes grouped by row-tile count and scaling
+      std::map<std::pair<int, int>, std::vector<fdk::SlabDesc>, std::greater<std::pair<int, int>>> groups;
+      for (const fd_work& wk : b->works) {
+        fdk::SlabDesc d;
+        if (!slab_pass(wk.plan, wk, stage, d)) continue;
+        groups[{slab_mt(wk.plan), d.scale ? 1 : 0}].push_back(d);
+      }
+      for (auto& [key, D] : groups) {
+        int64_t t = 0;
+        int max_n = 0;
+        for (auto& d : D) {
+          d.tile_begin = t;
+          t += int64_t(d.n3) * d.nrhs;
+          max_n = std::max(max_n, std::max(d.n1, d.n2));
+        }
+        if (t > 0x7fffffffLL) return fail(FD_E_ARG, "fd_batch_create: too many tiles in one launch");
+        fd_batch_s::StagedLaunch L{stage, key.first, key.second == 1, put(D.data(), D.size() * sizeof(fdk::SlabDesc)),
+                                   int(D.size()), t, 0, max_n};
+        b->staged.push_back(L);
+      }
+    }
+  }
+  hipError_t e = hipMalloc(&b->sdev, image.size());
+  if (e != hipSuccess) {
+    b->sdev = nullptr;
+    b->staged.clear();
+    return e == hipErrorOutOfMemory ? fail(FD_E_NOMEM, "fd_batch") : hip_fail(e, "hipMalloc");
+  }
+  e = hipMemcpy(b->sdev, image.data(), image.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  return FD_OK;
+}
+
+// The staged route: its launches in stage order on `stream`.
+static fd_status batch_launch_staged(fd_batch_s* b, hipStream_t stream) {
+  const int cls = b->prec == FD_BF16 ? 7 : 8;
+  StageRecord rec{-1, nullptr, nullptr};
+  auto close_stage = [&]() -> fd_status {
+    if (!rec.start) return FD_OK;
+    hipError_t e = hipEventRecord(rec.end, stream);
+    if (e != hipSuccess) return hip_fail(e, "timing event");
+    g_records.push_back(rec);
+    rec = StageRecord{-1, nullptr, nullptr};
+    return FD_OK;
+  };
+  for (const auto& L : b->staged) {
+    if (g_timing && L.stage != rec.stage) {
+      fd_status s = close_stage();
+      if (s != FD_OK) return s;
+      rec.stage = L.stage;
+      hipError_t e = hipEventCreate(&rec.start);
+      if (e == hipSuccess) e = hipEventCreate(&rec.end);
+      if (e == hipSuccess) e = hipEventRecord(rec.start, stream);
+      if (e != hipSuccess) return hip_fail(e, "timing event");
+    }
+    LaunchRecord lr{L.stage, L.stage == 2 ? 3 : 5, L.max_n, L.stage == 2 ? cls : b->prec, nullptr, nullptr};
+    if (g_timing) {
+      hipError_t e = hipEventCreate(&lr.start);
+      if (e == hipSuccess) e = hipEventCreate(&lr.end);
+      if (e == hipSuccess) e = hipEventRecord(lr.start, stream);
+      if (e != hipSuccess) return hip_fail(e, "timing event");
+    }
+    const unsigned char* base = static_cast<const unsigned char*>(b->sdev) + L.off;
+    hipError_t e;
+    if (L.stage == 2) {
+      fdk::BatchSeg sg{};
+      sg.d0 = 0;
+      sg.d1 = L.count;
+      sg.t0 = 0;
+      sg.t1 = int(L.tiles);
+      sg.mode = 2;
+      sg.mt = L.mt;
+      sg.body = fdk::kBodyPipelined;
+      e = fdk::launch_seg3(reinterpret_cast<const fdk::BatchDesc*>(base), sg, cls, L.mt, L.smem, stream);
+    } else {
+      fdk::SlabTab t{reinterpret_cast<const fdk::SlabDesc*>(base), L.count, int(L.tiles)};
+      e = fdk::launch_slab_tab(t, b->prec, L.mt, L.stage == 0, L.sc, stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "staged batch launch");
+    if (g_timing) {
+      e = hipEventRecord(lr.end, stream);
+      if (e != hipSuccess) return hip_fail(e, "timing event");
+      g_launch_records.push_back(lr);
+    }
+  }
+  return close_stage();
 }
 
 // ---------------------------------------------------------------- allocation-free persistent apply
@@ -1349,6 +1520,7 @@ fd_status fd_batch_create(int32_t count, const fd_work* work, fd_batch* out) {
       if (b->lay[0].tiles[st] > 0) ++b->phases;
     s = batch_upload(b);
   }
+  if (s == FD_OK) s = batch_build_staged(b);
   if (s == FD_OK) {
     e = hipMalloc(&b->ctl, 256);
     if (e == hipSuccess) e = hipMemset(b->ctl, 0, 256);
@@ -1387,6 +1559,7 @@ fd_status fd_batch_tune(fd_batch b, void* stream, int32_t reps, int32_t* choice)
   };
   // greedy over stages: each stage keeps the body choice that made the whole
   // apply fastest, given the choices already made for the earlier stages
+  b->use_staged = false;
   for (int i = 0; i < kStages; ++i) b->width[i] = 0;
   fd_status s = batch_upload(b);
   float best = 0.0f;
@@ -1407,6 +1580,13 @@ fd_status fd_batch_tune(fd_batch b, void* stream, int32_t reps, int32_t* choice)
     b->width[stage] = keep;
   }
   if (s == FD_OK) s = batch_upload(b);
+  // the staged route, where the batch has one
+  if (s == FD_OK && !b->staged.empty()) {
+    b->use_staged = true;
+    float ms = 0.0f;
+    s = time_current(&ms);
+    b->use_staged = s == FD_OK && ms < best;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (s != FD_OK) return s;
@@ -1416,7 +1596,16 @@ fd_status fd_batch_tune(fd_batch b, void* stream, int32_t reps, int32_t* choice)
 }
 
 fd_status fd_batch_set_config(fd_batch b, int32_t config) {
+  if (b && config == kBatchStaged) {
+    if (b->staged.empty())
+      return fail(FD_E_UNSUPPORTED, "fd_batch_set_config: the batch has no staged route (not all slab-route plans)");
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "fd_batch_set_config");
+    b->use_staged = true;
+    return FD_OK;
+  }
   if (!b || config < 0 || config >= (1 << (2 * kStages))) return fail(FD_E_ARG, "fd_batch_set_config: bad arguments");
+  b->use_staged = false;
   for (int st = 0; st < kStages; ++st)
     if (((config >> (2 * st)) & 3) == 3) return fail(FD_E_ARG, "fd_batch_set_config: body choice 3");
   for (int st = 0; st < kStages; ++st) b->width[st] = (config >> (2 * st)) & 3;
@@ -1427,10 +1616,13 @@ fd_status fd_batch_info(fd_batch b, int64_t* tiles, int32_t* grid, int32_t* conf
   if (!b) return fail(FD_E_ARG, "fd_batch_info: NULL batch");
   if (tiles) {
     int64_t t = 0;
-    for (int st = 0; st < kStages; ++st) t += b->lay[b->width[st]].tiles[st];
+    if (b->use_staged)
+      for (const auto& L : b->staged) t += L.tiles;
+    else
+      for (int st = 0; st < kStages; ++st) t += b->lay[b->width[st]].tiles[st];
     *tiles = t;
   }
-  if (grid) *grid = int32_t(std::min<int64_t>(b->cus, b->max_tiles));
+  if (grid) *grid = int32_t(std::min<int64_t>(b->cus, b->max_tiles));  // (the persistent launch's)
   if (config) *config = batch_config(b);
   return FD_OK;
 }
@@ -1458,6 +1650,7 @@ fd_status fd_batch_destroy(fd_batch b) {
   if (!b) return FD_OK;
   if (b->dev) (void)hipFree(b->dev);
   if (b->ctl) (void)hipFree(b->ctl);
+  if (b->sdev) (void)hipFree(b->sdev);
   delete b;
   return FD_OK;
 }

@@ -133,11 +133,23 @@ struct SlabArgs {
   SlabDesc u[kMaxDesc];
 };
 
+// The units of a slab launch in a device table (fixed batches): u[0, count)
+// ordered by tile_begin. Each workgroup takes one contiguous range of slabs,
+// so that it restages the factors only where its range crosses into the
+// next unit.
+struct SlabTab {
+  const SlabDesc* u;
+  int32_t count;
+  int32_t total_tiles;
+};
+
 // 16-bit element offset of the 16-bit layout within each plane of A entries
 __host__ __device__ inline int64_t slab_off16(int64_t A) { return A & ~int64_t(1); }
 size_t slab_lds_bytes(int mt);
 // prec: 2 (BF16) or 3 (FP16); mt: row tiles of max(n1, n2), <= kSlabMaxMT
 hipError_t launch_slab(const SlabArgs& args, int prec, int mt, hipStream_t stream);
+// fwd: in16 == 0 for every unit; sc: every unit has a scale (the host groups so)
+hipError_t launch_slab_tab(const SlabTab& tab, int prec, int mt, bool fwd, bool sc, hipStream_t stream);
 
 // LDS bytes of the weighted-eigenvalue tables of a divide pass (w_0 d_0, w_1 d_1
 // and w_l d_l of every unit, FP64), placed after the pipeline ring.
@@ -165,6 +177,11 @@ int v2_max_mt_of(int prec);
 void v3_factor_f32(int n, const double* F, bool second, float scale, float* dst);
 hipError_t fp8s_image(const float* src, void* dst, int64_t entries, hipStream_t stream);
 hipError_t launch_pass3(const PassArgs& args, int prec, int mode, int mt, size_t smem, hipStream_t stream);
+// The fused last-mode pass of 16-bit data (classes 7, 8) over one segment of
+// a device table of passes (fixed batches; factor orders may differ per
+// pass): tiles [sg.t0, sg.t1), passes [sg.d0, sg.d1); mt as v3_plan.
+hipError_t launch_seg3(const BatchDesc* table, const BatchSeg& sg, int prec, int mt, size_t smem,
+                       hipStream_t stream);
 // Bytes of one plain factor (n x n in the storage type, hi and lo planes for split).
 // Batched persistent launch: pencils per tile and LDS bytes of a pass body,
 // resident workgroups per CU, launch, counter reset.

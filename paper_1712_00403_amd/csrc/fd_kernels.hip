@@ -201,6 +201,16 @@ hipError_t batch_resident(int prec, size_t smem, int* per_cu) {
   }
 }
 
+extern template hipError_t launch_seg3_p<7>(const BatchDesc*, const BatchSeg&, int, size_t, hipStream_t);
+extern template hipError_t launch_seg3_p<8>(const BatchDesc*, const BatchSeg&, int, size_t, hipStream_t);
+
+hipError_t launch_seg3(const BatchDesc* table, const BatchSeg& sg, int prec, int mt, size_t smem,
+                       hipStream_t stream) {
+  if (prec == 7) return launch_seg3_p<7>(table, sg, v3_mt(prec, mt), smem, stream);
+  if (prec == 8) return launch_seg3_p<8>(table, sg, v3_mt(prec, mt), smem, stream);
+  return hipErrorInvalidValue;
+}
+
 hipError_t batch_launch(const BatchArgs& args, int prec, int grid, size_t smem, hipStream_t stream) {
   switch (prec) {
     case 0: return batch_launch_p<0>(args, grid, smem, stream);

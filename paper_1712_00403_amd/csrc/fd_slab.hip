@@ -70,7 +70,17 @@ struct SlabPos {
   int ui, rhs, i3;
   bool valid;
 };
-__device__ __forceinline__ SlabPos slab_pos(const SlabArgs& args, int tile) {
+
+// Unit sources of a slab launch (free functions on the kernel argument).
+// Kernel-argument table (at most kMaxDesc units): slabs blockIdx.x +
+// k gridDim.x; the unit of a slab found by a scan of the table.
+__device__ __forceinline__ const SlabDesc& slab_unit(const SlabArgs& args, int ui) { return args.u[ui]; }
+__device__ __forceinline__ void slab_range(const SlabArgs& args, int* t0, int* t1, int* step) {
+  *t0 = (int)blockIdx.x;
+  *t1 = args.total_tiles;
+  *step = (int)gridDim.x;
+}
+__device__ __forceinline__ SlabPos slab_pos(const SlabArgs& args, int tile, const SlabPos&) {
   SlabPos p;
   p.valid = tile < args.total_tiles;
   int ui = 0;
@@ -84,14 +94,49 @@ __device__ __forceinline__ SlabPos slab_pos(const SlabArgs& args, int tile) {
   return p;
 }
 
+// Device table: a contiguous range of slabs per workgroup; the unit of the
+// first slab by bisection, of the following ones by stepping forward from
+// the previous slab's unit. The table is read through the constant address
+// space (scalar loads; it does not change during a launch).
+typedef const SlabDesc __attribute__((address_space(4))) SlabDescC;
+__device__ __forceinline__ SlabDescC& slab_unit(const SlabTab& t, int ui) { return ((SlabDescC*)t.u)[ui]; }
+__device__ __forceinline__ void slab_range(const SlabTab& t, int* t0, int* t1, int* step) {
+  const int G = (int)gridDim.x, w = (int)blockIdx.x;
+  const int per = t.total_tiles / G, rem = t.total_tiles - per * G;
+  *t0 = w * per + (w < rem ? w : rem);
+  *t1 = *t0 + per + (w < rem ? 1 : 0);
+  *step = 1;
+}
+__device__ __forceinline__ SlabPos slab_pos(const SlabTab& t, int tile, const SlabPos& hint) {
+  SlabPos p;
+  p.valid = tile < t.total_tiles;
+  int ui = hint.ui;
+  if (!hint.valid) {
+    int lo = 0, hi = t.count - 1;  // last unit whose first slab is <= tile
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (slab_unit(t, mid).tile_begin <= tile) lo = mid;
+      else hi = mid - 1;
+    }
+    ui = lo;
+  } else {
+    while (ui + 1 < t.count && slab_unit(t, ui + 1).tile_begin <= tile) ++ui;
+  }
+  p.ui = ui;
+  const int tl = p.valid ? tile - (int)slab_unit(t, ui).tile_begin : 0;
+  p.rhs = tl / slab_unit(t, ui).n3;
+  p.i3 = tl - p.rhs * slab_unit(t, ui).n3;
+  return p;
+}
+
 // FWD: the forward slab pass (FP32 input, pre-scaled by D^{-1/2} if SC, 16-bit
 // output); otherwise the backward one (16-bit input, FP32 output, post-scaled
 // if SC). Both are template parameters so that the load and store sequences
 // are straight-line code with a fixed number of memory instructions per
 // slab, which keeps the compiler's wait counts exact across the slab loop.
-template <int P, int MT, bool FWD, bool SC>
+template <int P, int MT, bool FWD, bool SC, class Src>
 __global__ __launch_bounds__(64 * kSlabWaves) __attribute__((amdgpu_waves_per_eu(3)))
-void fd_slab_kernel(const SlabArgs args) {
+void fd_slab_kernel(const Src args) {
   using S = typename SlabT<P>::s;
   using frag = typename SlabT<P>::frag;
   using v4 = typename SlabT<P>::v4;
@@ -130,7 +175,7 @@ void fd_slab_kernel(const SlabArgs args) {
   fl2 sa[SC ? KA : 1];
   float sb0[KB], sb1[KB];
   auto prefetch = [&](const SlabPos& q, int lane) {
-    const SlabDesc& u = args.u[q.ui];
+    auto& u = slab_unit(args, q.ui);
     const int n1 = u.n1, n2 = u.n2, A = n1 * n2;
     // (row offsets go in the scalar offset; an out-of-range vector offset
     // stays out of range with it: A * 4 < 2^31)
@@ -196,15 +241,13 @@ void fd_slab_kernel(const SlabArgs args) {
   // slab's stores could only be waited for together with them).
   v4 zh[TB][TB];
   f4 zf[TB][TB];
-  int prev = -1;
   // Z(j1, j2) of slab `tile`: lane group g's 16 lanes hold 16 consecutive
   // j1; every thread issues the same 4 TB^2 stores (invalid ones at an
   // out-of-range offset, dropped); offset = a per-lane vector part + a
   // uniform scalar part per tile and row
-  auto store_z = [&](int tile, int lane) {
+  auto store_z = [&](const SlabPos& ps, int lane) {
     const int g = lane >> 4, l16 = lane & 15;
-    const SlabPos ps = slab_pos(args, tile);
-    const SlabDesc& u = args.u[ps.ui];
+    auto& u = slab_unit(args, ps.ui);
     const int n1 = u.n1, n2 = u.n2, A = n1 * n2;
     constexpr int EB = FWD ? 2 : 4;
     const uint32_t vlane = (uint32_t)(l16 + 4 * g * n1) * EB;  // j1 = .. + l16, j2 = .. + 4 g
@@ -236,21 +279,22 @@ void fd_slab_kernel(const SlabArgs args) {
         }
       }
   };
-  {
-    const SlabPos q = slab_pos(args, blockIdx.x);
-    if (q.valid) prefetch(q, tid0 & 63);
-  }
+  int t_begin = 0, t_end = 0, t_step = 1;
+  slab_range(args, &t_begin, &t_end, &t_step);
+  SlabPos nxt = slab_pos(args, t_begin, SlabPos{0, 0, 0, false});
+  if (nxt.valid && t_begin < t_end) prefetch(nxt, tid0 & 63);
   int staged = -1;  // unit whose factors are in LDS
+  SlabPos prevp{0, 0, 0, false};  // the slab whose results wait in zh / zf
 
-  for (int tile = blockIdx.x; tile < args.total_tiles; tile += gridDim.x) {
+  for (int tile = t_begin; tile < t_end; tile += t_step) {
     // (the thread index passes through an empty asm each slab so that the
     // offsets derived from it are recomputed here rather than hoisted out of
     // the loop and spilled)
     int tid = tid0;
     asm volatile("" : "+v"(tid));
     const int lane = tid & 63, g = lane >> 4, l16 = lane & 15;
-    const SlabPos cur = slab_pos(args, tile);
-    const SlabDesc& u = args.u[cur.ui];
+    const SlabPos cur = nxt;
+    auto& u = slab_unit(args, cur.ui);
     const int n1 = u.n1, n2 = u.n2;
 
     // ---- the previous slab is done with the LDS
@@ -330,11 +374,9 @@ void fd_slab_kernel(const SlabArgs args) {
     }
     // the previous slab's stores, then the next slab's input, stream while
     // this one computes
-    if (prev >= 0) store_z(prev, lane);
-    {
-      const SlabPos nx = slab_pos(args, tile + gridDim.x);
-      if (nx.valid) prefetch(nx, lane);
-    }
+    if (prevp.valid) store_z(prevp, lane);
+    nxt = slab_pos(args, tile + t_step, cur);
+    if (nxt.valid && tile + t_step < t_end) prefetch(nxt, lane);
     slab_barrier();
 
     // Fragment reads: row 16 T + l16 (T uniform), chunk g of block s; the
@@ -418,14 +460,14 @@ void fd_slab_kernel(const SlabArgs args) {
         if constexpr (FWD) zh[t][q] = __builtin_convertvector(z, v4);
         else zf[t][q] = z;
       }
-    prev = tile;
+    prevp = cur;
   }
-  if (prev >= 0) store_z(prev, tid0 & 63);
+  if (prevp.valid) store_z(prevp, tid0 & 63);
 }
 
-template <int P, int MT, bool FWD, bool SC>
-static hipError_t launch_slab_m(const SlabArgs& args, hipStream_t stream) {
-  auto kern = fd_slab_kernel<P, MT, FWD, SC>;
+template <int P, int MT, bool FWD, bool SC, class Src>
+static hipError_t launch_slab_m(const Src& args, hipStream_t stream) {
+  auto kern = fd_slab_kernel<P, MT, FWD, SC, Src>;
   const size_t smem = slab_lds_bytes(MT);
   // once per process (thread-safe initialisation of a function-local static)
   static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -454,14 +496,15 @@ static hipError_t launch_slab_m(const SlabArgs& args, hipStream_t stream) {
   return hipGetLastError();
 }
 
-template <int P, int MT>
-static hipError_t launch_slab_mt(const SlabArgs& args, bool fwd, bool sc, hipStream_t stream) {
-  if (fwd) return sc ? launch_slab_m<P, MT, true, true>(args, stream) : launch_slab_m<P, MT, true, false>(args, stream);
+template <int P, int MT, class Src>
+static hipError_t launch_slab_mt(const Src& args, bool fwd, bool sc, hipStream_t stream) {
+  if (fwd)
+    return sc ? launch_slab_m<P, MT, true, true>(args, stream) : launch_slab_m<P, MT, true, false>(args, stream);
   return sc ? launch_slab_m<P, MT, false, true>(args, stream) : launch_slab_m<P, MT, false, false>(args, stream);
 }
 
-template <int P, int... I>
-static hipError_t launch_slab_sel(const SlabArgs& args, int mt, bool fwd, bool sc, hipStream_t stream,
+template <int P, class Src, int... I>
+static hipError_t launch_slab_sel(const Src& args, int mt, bool fwd, bool sc, hipStream_t stream,
                                   std::integer_sequence<int, I...>) {
   hipError_t res = hipErrorInvalidValue;
   (void)((mt == I + 1 ? (res = launch_slab_mt<P, I + 1>(args, fwd, sc, stream), true) : false) || ...);
@@ -477,6 +520,15 @@ hipError_t launch_slab(const SlabArgs& args, int prec, int mt, hipStream_t strea
   using seq = std::make_integer_sequence<int, kSlabMaxMT>;
   if (prec == 2) return launch_slab_sel<2>(args, mt, fwd, sc, stream, seq{});
   if (prec == 3) return launch_slab_sel<3>(args, mt, fwd, sc, stream, seq{});
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_slab_tab(const SlabTab& tab, int prec, int mt, bool fwd, bool sc, hipStream_t stream) {
+  if (tab.total_tiles <= 0) return hipSuccess;
+  if (tab.count < 1 || !tab.u) return hipErrorInvalidValue;
+  using seq = std::make_integer_sequence<int, kSlabMaxMT>;
+  if (prec == 2) return launch_slab_sel<2>(tab, mt, fwd, sc, stream, seq{});
+  if (prec == 3) return launch_slab_sel<3>(tab, mt, fwd, sc, stream, seq{});
   return hipErrorInvalidValue;
 }
 

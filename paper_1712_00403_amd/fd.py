@@ -393,6 +393,9 @@ class Batch:
         _check(lib().fd_batch_apply(self.handle, _stream_handle(stream)))
 
     WIDE, NARROW, PIPELINED = 0, 1, 2  # body choices of a stage
+    # configuration word of the staged route (every work a 3D BF16/FP16
+    # slab-route plan): one launch per stage and row-tile group
+    STAGED = 1 << 10
 
     @staticmethod
     def config_of(choices):
@@ -404,7 +407,8 @@ class Batch:
         return [(int(config) >> (2 * s)) & 3 for s in range(5)]
 
     def tune(self, stream=None, reps=3):
-        """Choose the body of every stage by timing (greedy); returns the configuration word."""
+        """Choose the body of every stage by timing (greedy), then the staged route if the batch
+        has one and it is faster; returns the configuration word."""
         c = ctypes.c_int32(0)
         _check(lib().fd_batch_tune(self.handle, _stream_handle(stream), int(reps), ctypes.byref(c)))
         return c.value

@@ -145,6 +145,110 @@ def test_persistent_batch_tuning_keeps_results():
         pc.close()
 
 
+# 3D patches only (every work a slab-route plan in BF16/FP16): the staged route
+STAGED_PATCHES = [i for i, (n_el, _, _) in enumerate(PATCHES) if len(n_el) == 3]
+
+
+def _batch_io(pcs, idx, nrhs, seed0, dt):
+    rs, zs, works = [], [], []
+    for i in idx:
+        pc = pcs[i]
+        r = workloads.residuals(seed0 + i, nrhs, pc.N)
+        rt = torch.from_numpy(r).to(dt).cuda()
+        zt = torch.full_like(rt, float("nan"))
+        rs.append(r)
+        zs.append((rt, zt))
+        works += pc.works(rt.data_ptr(), zt.data_ptr(), nrhs)
+    return rs, zs, works
+
+
+@pytest.mark.parametrize("prec", ["bf16", "f16"])
+def test_staged_route_matches_oracle(prec):
+    """The staged route of a batch of 3D patches (simple and coefficient-aware blocks):
+    slab passes and the 16-bit fused pass over device tables, one launch per stage and
+    row-tile group. Compared with the oracle element-wise, repeated bitwise, in place
+    (z == r), and against the persistent route of the same batch within the tolerance."""
+    _case(f"staged batch route of {len(STAGED_PATCHES)} 3D patches, prec={prec}")
+    from paper_1712_00403_amd import fd
+    pcs, refs = _build(prec)
+    nrhs = 2
+    rs, zs, works = _batch_io(pcs, STAGED_PATCHES, nrhs, 90, torch.float32)
+    batch = fd.Batch(works)
+    batch.set_config(fd.Batch.STAGED)
+    assert batch.info()["config"] == fd.Batch.STAGED
+    fd.timing_enable(True)
+    try:
+        batch.apply()
+        torch.cuda.synchronize()
+        fd.timing_read()
+        fams = {(rec["stage"], rec["family"]) for rec in fd.timing_launches()}
+    finally:
+        fd.timing_enable(False)
+    assert fams == {("mode1_fwd", 5), ("last_mode_fused", 3), ("mode1_bwd", 5)}, fams
+    outs = []
+    for rep in range(2):
+        for _, zt in zs:
+            zt.fill_(float("nan"))
+        batch.apply()
+        batch.check()
+        torch.cuda.synchronize()
+        outs.append([zt.cpu().numpy().astype(np.float64) for _, zt in zs])
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b), "two applies of one batch differ"
+    for k, i in enumerate(STAGED_PATCHES):
+        facs, Mp, ps, vs = refs[i]
+        for j in range(nrhs):
+            zo = block_apply(facs, Mp, rs[k][j], pres_scale=ps, vel_scales=vs)
+            for a, b in zip(pcs[i].offsets[:-1], pcs[i].offsets[1:]):
+                check_close(outs[0][k][j, a:b], zo[a:b], prec, f"patch {i} block [{a},{b}) residual {j}")
+    # the persistent route of the same works
+    batch.set_config(0)
+    for _, zt in zs:
+        zt.fill_(float("nan"))
+    batch.apply()
+    batch.check()
+    torch.cuda.synchronize()
+    for k, (_, zt) in enumerate(zs):
+        zp = zt.cpu().numpy().astype(np.float64)
+        for j in range(nrhs):
+            e = np.linalg.norm(zp[j] - outs[0][k][j]) / np.linalg.norm(zp[j])
+            assert e < TOL[prec], f"patch {STAGED_PATCHES[k]}: routes differ by {e:.3e}"
+    batch.close()
+    # in place: z == r
+    rs2, zs2, works2 = [], [], []
+    for k, i in enumerate(STAGED_PATCHES):
+        rt = torch.from_numpy(rs[k]).float().cuda()
+        zs2.append(rt)
+        works2 += pcs[i].works(rt.data_ptr(), rt.data_ptr(), nrhs)
+    batch = fd.Batch(works2)
+    batch.set_config(fd.Batch.STAGED)
+    batch.apply()
+    batch.check()
+    torch.cuda.synchronize()
+    for k, rt in enumerate(zs2):
+        assert np.array_equal(rt.cpu().numpy().astype(np.float64), outs[0][k]), "in-place staged apply differs"
+    batch.close()
+    for pc in pcs:
+        pc.close()
+
+
+def test_staged_route_availability():
+    """Only batches whose works are all 3D BF16/FP16 slab-route plans have the staged route."""
+    _case("staged route availability")
+    from paper_1712_00403_amd import fd
+    for prec, idx in (("f32", STAGED_PATCHES), ("bf16", list(range(len(PATCHES))))):
+        pcs, _ = _build(prec)
+        _, _, works = _batch_io(pcs, idx, 1, 95, torch.float32)
+        batch = fd.Batch(works)
+        with pytest.raises(fd.FDError):
+            batch.set_config(fd.Batch.STAGED)
+        cfg = batch.tune(reps=1)
+        assert cfg != fd.Batch.STAGED
+        batch.close()
+        for pc in pcs:
+            pc.close()
+
+
 def test_persistent_batch_rejects_large_factors():
     _case("persistent batch argument checks")
     from paper_1712_00403_amd import fd
@@ -250,6 +354,14 @@ def test_c4_batch_256_patches_largest_and_drawn(prec):
     torch.cuda.synchronize()
     e = check_c4_samples(Z.double().cpu().numpy(), offs, pcs, c4, prec, f"tuned config {cfg}")
     print(f"  tuned config {cfg}: sampled rel err {e[0]:.3e}, rel max err {e[1]:.3e}")
+    if prec == "bf16":  # the staged route (every patch is a slab-route plan)
+        batch.set_config(fd.Batch.STAGED)
+        Z.fill_(float("nan"))
+        batch.apply()
+        batch.check()
+        torch.cuda.synchronize()
+        e = check_c4_samples(Z.double().cpu().numpy(), offs, pcs, c4, prec, "staged route")
+        print(f"  staged route: sampled rel err {e[0]:.3e}, rel max err {e[1]:.3e}")
     batch.close()
     for pc in pcs:
         pc.close()
