@@ -292,6 +292,17 @@ fd_status fd_apply_batched(int32_t count, const fd_work* work, void* stream);
  * (*choice = the configuration word). An untuned batch runs every stage
  * wide. Tuning synchronizes the device.
  *
+ * Staged route (configuration word 1 << 10): when every work of the batch is
+ * a 3D BF16/FP16 plan on the slab route (Sec. 5.2, Algorithm 1 steps 2-4 as
+ * a slab pass over the two in-plane modes, the fused last-mode pass and a
+ * slab pass back, the tensor kept in 16 bits inside z in between), an apply
+ * is instead one launch per stage and row-tile group (at most 3 x 9), each
+ * reading its units from a table built at creation; no grid barrier, so it
+ * needs no co-resident grid. fd_batch_tune times it after the greedy search
+ * and keeps it if faster; fd_batch_set_config(1 << 10) on a batch without
+ * it is FD_E_UNSUPPORTED. Results agree with the persistent route within the
+ * precision's rounding (the routes round intermediates differently).
+ *
  * Applies of one batch must be ordered (one stream, or synchronized): they
  * share the barrier counter. A barrier wait is bounded: if the grid cannot be
  * fully resident (other kernels occupy the device), the waits give up after
@@ -305,7 +316,8 @@ fd_status fd_batch_create(int32_t count, const fd_work* work, fd_batch* out);
 fd_status fd_batch_apply(fd_batch batch, void* stream);
 fd_status fd_batch_tune(fd_batch batch, void* stream, int32_t reps, int32_t* choice);
 /* Sets the body choices directly (a configuration word, e.g. from an earlier
- * tune; a choice of 3 is FD_E_ARG); synchronizes the device. */
+ * tune; a choice of 3 is FD_E_ARG; 1 << 10 selects the staged route);
+ * synchronizes the device. */
 fd_status fd_batch_set_config(fd_batch batch, int32_t config);
 /* Tiles per apply, grid size and configuration word. */
 fd_status fd_batch_info(fd_batch batch, int64_t* tiles, int32_t* grid, int32_t* config);

@@ -41,6 +41,7 @@ struct fd_plan_s {
   float xs[5] = {1, 1, 1, 1, 1}, qs = 1.0f;             // FP16 / FP8 range scaling per stage
   float fs[3] = {1, 1, 1};                              // FP8: scale of the factor images per direction
   const void* scale_dev = nullptr;                      // D^{-1/2}, I/O type
+  const void* scale16 = nullptr;                        // slab route: D^{-1/2} in 16 bits (SlabDesc::scale)
   int MT[3] = {0, 0, 0}, KS[3] = {0, 0, 0};
   int device = 0;
   int family_cap = 3;  // most capable kernel family the plan's passes may use
@@ -90,7 +91,7 @@ struct fd_batch_s {
   struct StagedLaunch {
     int stage;        // 0, 2 or 4
     int mt;           // slab: row tiles of max(n1, n2); fused: of the last order
-    bool sc;          // slab: the units scale by D^{-1/2}
+    bool sc;          // slab: the units scale by D^{-1/2}; fused: eigenvalue tables in LDS
     size_t off;       // byte offset of the units (SlabDesc or BatchDesc) in sdev
     int count;        // units
     int64_t tiles;
@@ -232,7 +233,7 @@ bool slab_pass(const fd_plan_s* p, const fd_work& wk, int stage, fdk::SlabDesc& 
   d.out = wk.z;
   d.f1 = fwd ? p->v_fwd[0] : p->v_bwd[0];
   d.f2 = fwd ? p->v_fwd[1] : p->v_bwd[1];
-  d.scale = static_cast<const float*>(p->scale_dev);
+  d.scale = p->scale16;
   d.post = fwd ? 0 : 1;
   d.ld = wk.ld;
   d.n1 = p->n[0];
@@ -754,6 +755,7 @@ static fd_status batch_build_staged(fd_batch_s* b) {
       // fused passes grouped by the (even) row-tile count of the last order
       std::map<int, std::vector<fdk::BatchDesc>, std::greater<int>> groups;
       std::map<int, std::pair<size_t, int>> plan_of;  // group -> (LDS bytes, largest order)
+      std::map<int, size_t> lam_of;                     // group -> largest eigenvalue table
       for (const fd_work& wk : b->works) {
         fdk::PassDesc u;
         if (wk.nrhs == 0 || !unit_pass(wk.plan, wk, 2, u)) continue;
@@ -771,6 +773,8 @@ static fd_status batch_build_staged(fd_batch_s* b) {
         auto& pl = plan_of[mt];
         pl.first = sm;
         pl.second = std::max(pl.second, u.n);
+        auto& tb = lam_of[mt];  // the unit's weighted eigenvalues in LDS (FP64)
+        tb = std::max(tb, sizeof(double) * size_t(u.n1 + u.A / u.n1 + u.n));
       }
       for (auto& [mt, D] : groups) {
         int64_t t = 0;
@@ -779,8 +783,10 @@ static fd_status batch_build_staged(fd_batch_s* b) {
           t += int64_t(bd.u.tiles_per_rhs) * bd.u.nrhs;
         }
         if (t > 0x7fffffffLL) return fail(FD_E_ARG, "fd_batch_create: too many tiles in one launch");
-        fd_batch_s::StagedLaunch L{2, mt, false, put(D.data(), D.size() * sizeof(fdk::BatchDesc)), int(D.size()),
-                                   t, plan_of[mt].first, plan_of[mt].second};
+        // the eigenvalue tables sit after the ring when they fit the LDS
+        const bool lam = plan_of[mt].first + lam_of[mt] <= 160 * 1024;
+        fd_batch_s::StagedLaunch L{2, mt, lam, put(D.data(), D.size() * sizeof(fdk::BatchDesc)), int(D.size()),
+                                   t, plan_of[mt].first + (lam ? lam_of[mt] : 0), plan_of[mt].second};
         b->staged.push_back(L);
       }
     } else {
@@ -817,7 +823,28 @@ static fd_status batch_build_staged(fd_batch_s* b) {
   return FD_OK;
 }
 
-// The staged route: its launches in stage order on `stream`.
+static hipError_t staged_launch_one(fd_batch_s* b, const fd_batch_s::StagedLaunch& L, hipStream_t stream) {
+  const int cls = b->prec == FD_BF16 ? 7 : 8;
+  const unsigned char* base = static_cast<const unsigned char*>(b->sdev) + L.off;
+  if (L.stage == 2) {
+    fdk::BatchSeg sg{};
+    sg.d0 = 0;
+    sg.d1 = L.count;
+    sg.t0 = 0;
+    sg.t1 = int(L.tiles);
+    sg.mode = 2;
+    sg.mt = L.mt;
+    sg.scale = L.sc ? 1 : 0;  // (fused launches: the eigenvalue tables go to LDS)
+    sg.body = fdk::kBodyPipelined;
+    return fdk::launch_seg3(reinterpret_cast<const fdk::BatchDesc*>(base), sg, cls, L.mt, L.smem, stream);
+  }
+  fdk::SlabTab t{reinterpret_cast<const fdk::SlabDesc*>(base), L.count, int(L.tiles)};
+  return fdk::launch_slab_tab(t, b->prec, L.mt, L.stage == 0, L.sc, stream);
+}
+
+// The staged route: its launches in stage order on `stream`. (Launching the
+// independent launches of a stage on forked streams gained nothing: each
+// launch fills the device.)
 static fd_status batch_launch_staged(fd_batch_s* b, hipStream_t stream) {
   const int cls = b->prec == FD_BF16 ? 7 : 8;
   StageRecord rec{-1, nullptr, nullptr};
@@ -846,22 +873,7 @@ static fd_status batch_launch_staged(fd_batch_s* b, hipStream_t stream) {
       if (e == hipSuccess) e = hipEventRecord(lr.start, stream);
       if (e != hipSuccess) return hip_fail(e, "timing event");
     }
-    const unsigned char* base = static_cast<const unsigned char*>(b->sdev) + L.off;
-    hipError_t e;
-    if (L.stage == 2) {
-      fdk::BatchSeg sg{};
-      sg.d0 = 0;
-      sg.d1 = L.count;
-      sg.t0 = 0;
-      sg.t1 = int(L.tiles);
-      sg.mode = 2;
-      sg.mt = L.mt;
-      sg.body = fdk::kBodyPipelined;
-      e = fdk::launch_seg3(reinterpret_cast<const fdk::BatchDesc*>(base), sg, cls, L.mt, L.smem, stream);
-    } else {
-      fdk::SlabTab t{reinterpret_cast<const fdk::SlabDesc*>(base), L.count, int(L.tiles)};
-      e = fdk::launch_slab_tab(t, b->prec, L.mt, L.stage == 0, L.sc, stream);
-    }
+    hipError_t e = staged_launch_one(b, L, stream);
     if (e != hipSuccess) return hip_fail(e, "staged batch launch");
     if (g_timing) {
       e = hipEventRecord(lr.end, stream);
@@ -1284,6 +1296,14 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
   }
   const size_t eb = io_is_f64(p->prec) ? 8 : 4;
   if (diag_target) { offs = total; total = align(total + eb * size_t(p->N)); }
+  // slab route: D^{-1/2} once more in the plan's 16-bit type, rows padded to
+  // an even length, so that the slab passes read it in aligned pairs
+  size_t offs16 = 0;
+  const int64_t n1p = n[0] + (n[0] & 1);
+  if (diag_target && p->slab) {
+    offs16 = total;
+    total = align(total + 2 * size_t(n1p) * n[1] * n[2]);
+  }
   std::vector<unsigned char> host(total, 0);
   std::vector<double> Ft;
   std::vector<float> stage8[3];
@@ -1317,6 +1337,23 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
     if (eb == 8) std::memcpy(host.data() + offs, scale.data(), 8 * size_t(p->N));
     else
       for (int64_t k = 0; k < p->N; ++k) reinterpret_cast<float*>(host.data() + offs)[k] = float(scale[k]);
+  }
+  if (diag_target && p->slab) {
+    uint16_t* s16 = reinterpret_cast<uint16_t*>(host.data() + offs16);
+    for (int64_t k = 0; k < int64_t(n[1]) * n[2]; ++k)
+      for (int i1 = 0; i1 < n[0]; ++i1) {
+        const float v = float(scale[k * n[0] + i1]);
+        uint16_t h;
+        if (p->prec == FD_BF16) {
+          uint32_t b;
+          std::memcpy(&b, &v, 4);
+          h = uint16_t((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);  // round to nearest even
+        } else {
+          const _Float16 f = (_Float16)v;
+          std::memcpy(&h, &f, 2);
+        }
+        s16[k * n1p + i1] = h;
+      }
   }
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) { delete p; return hip_fail(e, "hipGetDevice"); }
@@ -1365,6 +1402,7 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
     p->d_dev[i] = reinterpret_cast<const double*>(base + offd[i]);
   }
   if (diag_target) p->scale_dev = base + offs;
+  if (diag_target && p->slab) p->scale16 = base + offs16;
   *out = p;
   return FD_OK;
 }

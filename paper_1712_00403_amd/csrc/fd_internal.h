@@ -115,7 +115,9 @@ struct SlabDesc {
   void* out;            // z: FP32 (out16 == 0) or the 16-bit layout
   const void* f1;       // padded row-major factor image of the product along i1 (ldf1 entries a row)
   const void* f2;       // the same along i2
-  const float* scale;   // D^{-1/2} (N entries) applied on load (pre) or store (post), or null
+  const void* scale;    // D^{-1/2} in the 16-bit type, applied on load (pre) or store (post), or
+                        // null; plane i3 at (n1 + (n1 & 1)) n2 i3, rows of n1 + (n1 & 1) entries
+                        // (an odd row ends with a zero)
   int64_t ld;           // FP32 elements between residual vectors
   int64_t tile_begin;   // first slab of this unit within the launch
   int32_t n1, n2, n3, nrhs;

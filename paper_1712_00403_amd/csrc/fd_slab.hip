@@ -44,6 +44,10 @@ __host__ __device__ constexpr int slab_kt(int mt) { return (mt + 1) / 2; }
 __host__ __device__ constexpr int slab_bs(int mt) { return 16 * mt * 64 + 64; }
 
 size_t slab_lds_bytes(int mt) { return 3 * size_t(slab_kt(mt)) * size_t(slab_bs(mt)); }
+// backward passes with a scale and at most 7 row tiles: the slab's D^{-1/2}
+// in LDS as well (16 mt rows of 16 mt + 16 entries, 16-bit)
+__host__ __device__ constexpr bool slab_scale_lds(bool fwd, bool sc, int mt) { return !fwd && sc && mt <= 7; }
+__host__ __device__ constexpr int slab_sci_bytes(int mt) { return 16 * mt * (16 * mt + 16) * 2; }
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
@@ -159,6 +163,11 @@ void fd_slab_kernel(const Src args) {
   unsigned char* const xs = lds;            // X, then Y (16-bit)
   unsigned char* const fs1 = lds + XB;      // F1 rows j1, columns i1
   unsigned char* const fs2 = lds + 2 * XB;  // F2 rows j2, columns i2
+  // backward pass with a scale: D^{-1/2} of the slab in LDS (SCL; row j2,
+  // n1p + 16 entries a row) for the epilogue, or (orders above 112) loaded
+  // one slab ahead into registers (SCB)
+  constexpr bool SCL = slab_scale_lds(FWD, SC, MT);
+  unsigned char* const sci = lds + 3 * XB;
 
   const int tid0 = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid0 >> 6);
@@ -172,8 +181,13 @@ void fd_slab_kernel(const Src args) {
   // tail pair.
   u32x2 xa[KA];
   uint32_t xp[FWD ? 1 : KA], xb0[KB], xb1[KB];
-  fl2 sa[SC ? KA : 1];
-  float sb0[KB], sb1[KB];
+  // D^{-1/2} in 16 bits, rows of n1 + (n1 & 1) entries (SlabDesc::scale):
+  // sa[k] the pair (2l, 2l + 1) of row k's, sbp[k] the tail pair
+  uint32_t sa[SC ? KA : 1], sbp[SC ? KB : 1];
+  auto scale2 = [](uint32_t w) -> fl2 {
+    const s2 h = __builtin_bit_cast(s2, w);
+    return fl2{(float)h[0], (float)h[1]};
+  };
   auto prefetch = [&](const SlabPos& q, int lane) {
     auto& u = slab_unit(args, q.ui);
     const int n1 = u.n1, n2 = u.n2, A = n1 * n2;
@@ -182,17 +196,23 @@ void fd_slab_kernel(const Src args) {
     if constexpr (FWD) {
       const __amdgpu_buffer_rsrc_t rin =
           make_rsrc(reinterpret_cast<const float*>(u.in) + ((int64_t)q.rhs * u.ld + (int64_t)A * q.i3), (uint32_t)A * 4);
-      const __amdgpu_buffer_rsrc_t rsc = make_rsrc(SC ? u.scale + (int64_t)A * q.i3 : nullptr, SC ? (uint32_t)A * 4 : 0u);
+      const int n1p = n1 + (n1 & 1);
+      const __amdgpu_buffer_rsrc_t rsc =
+          make_rsrc(SC ? static_cast<const S*>(u.scale) + (int64_t)n1p * n2 * q.i3 : nullptr,
+                    SC ? (uint32_t)(n1p * n2) * 2 : 0u);
       // pair (2l, 2l + 1); the lone last entry of an odd row (2l = n1 - 1)
-      // comes as the second half of the pair (2l - 1, 2l)
+      // comes as the second half of the pair (2l - 1, 2l) (its scale as the
+      // first half of the scale pair (2l, 2l + 1), the second a zero pad)
       const uint32_t vf = 2 * lane + 1 < n1 ? (uint32_t)(8 * lane) : 2 * lane + 1 == n1 ? (uint32_t)(8 * lane - 4) : kOOB;
+      const uint32_t vs = 2 * lane < n1 ? (uint32_t)(4 * lane) : kOOB;
 #pragma unroll
       for (int k = 0; k < KA; ++k) {
         const int r = wave + W * k;
         const int so = (r < n2 ? r : 0) * n1 * 4;
         const uint32_t of = r < n2 ? vf : kOOB;
         xa[k] = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rin, of, so, 0));
-        if constexpr (SC) sa[k] = __builtin_bit_cast(fl2, __builtin_amdgcn_raw_buffer_load_b64(rsc, of, so, 0));
+        if constexpr (SC)
+          sa[k] = __builtin_amdgcn_raw_buffer_load_b32(rsc, r < n2 ? vs : kOOB, (r < n2 ? r : 0) * n1p * 2, 0);
       }
       if constexpr (TAILC) {
 #pragma unroll
@@ -202,10 +222,9 @@ void fd_slab_kernel(const Src args) {
           const uint32_t o1 = r < n2 && c + 1 < n1 ? (uint32_t)((r * n1 + c + 1) * 4) : kOOB;
           xb0[k] = __builtin_amdgcn_raw_buffer_load_b32(rin, o0, 0, 0);
           xb1[k] = __builtin_amdgcn_raw_buffer_load_b32(rin, o1, 0, 0);
-          if constexpr (SC) {
-            sb0[k] = bload(rsc, o0, (float*)nullptr);
-            sb1[k] = bload(rsc, o1, (float*)nullptr);
-          }
+          if constexpr (SC)
+            sbp[k] = __builtin_amdgcn_raw_buffer_load_b32(
+                rsc, r < n2 && c < n1 ? (uint32_t)((r * n1p + c) * 2) : kOOB, 0, 0);
         }
       }
     } else {
@@ -214,12 +233,19 @@ void fd_slab_kernel(const Src args) {
           (uint32_t)A * 2);
       const uint32_t v0 = 2 * lane < n1 ? (uint32_t)(4 * lane) : kOOB;
       const uint32_t v1 = 2 * lane + 1 < n1 ? (uint32_t)(4 * lane + 2) : kOOB;
+      const int n1p = n1 + (n1 & 1);
+      const __amdgpu_buffer_rsrc_t rsc =
+          make_rsrc(SCL ? static_cast<const S*>(u.scale) + (int64_t)n1p * n2 * q.i3 : nullptr,
+                    SCL ? (uint32_t)(n1p * n2) * 2 : 0u);
+      const uint32_t vs = 2 * lane < n1 ? (uint32_t)(4 * lane) : kOOB;
 #pragma unroll
       for (int k = 0; k < KA; ++k) {
         const int r = wave + W * k;
         const int so = (r < n2 ? r : 0) * n1 * 2;
         xa[k][0] = __builtin_amdgcn_raw_buffer_load_b16(rin, r < n2 ? v0 : kOOB, so, 0);
         xp[k] = __builtin_amdgcn_raw_buffer_load_b16(rin, r < n2 ? v1 : kOOB, so, 0);
+        if constexpr (SCL)
+          sa[k] = __builtin_amdgcn_raw_buffer_load_b32(rsc, r < n2 ? vs : kOOB, (r < n2 ? r : 0) * n1p * 2, 0);
       }
       if constexpr (TAILC) {
 #pragma unroll
@@ -241,6 +267,11 @@ void fd_slab_kernel(const Src args) {
   // slab's stores could only be waited for together with them).
   v4 zh[TB][TB];
   f4 zf[TB][TB];
+  // SCB: D^{-1/2} at the entries of zf, loaded one slab ahead of its use (a
+  // load right before the store that needs it would expose the memory
+  // latency in every slab)
+  constexpr bool SCB = !FWD && SC && !SCL;
+  f4 zsc[SCB ? TB : 1][SCB ? TB : 1];
   // Z(j1, j2) of slab `tile`: lane group g's 16 lanes hold 16 consecutive
   // j1; every thread issues the same 4 TB^2 stores (invalid ones at an
   // out-of-range offset, dropped); offset = a per-lane vector part + a
@@ -255,8 +286,6 @@ void fd_slab_kernel(const Src args) {
                               : (int64_t)ps.rhs * u.ld + (int64_t)A * ps.i3;
     const __amdgpu_buffer_rsrc_t rout = FWD ? make_rsrc(reinterpret_cast<S*>(u.out) + plane, (uint32_t)A * 2)
                                             : make_rsrc(reinterpret_cast<float*>(u.out) + plane, (uint32_t)A * 4);
-    const __amdgpu_buffer_rsrc_t rsc = make_rsrc(!FWD && SC ? u.scale + (int64_t)A * ps.i3 : nullptr,
-                                                 !FWD && SC ? (uint32_t)A * 4 : 0u);
 #pragma unroll
     for (int t = 0; t < TB; ++t)
 #pragma unroll
@@ -273,9 +302,32 @@ void fd_slab_kernel(const Src args) {
             bstore16(rout, vo, so, zh[t][q][r]);
           } else {
             float zr = zf[t][q][r];
-            if constexpr (SC) zr *= __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rsc, vo, so, 0));
+            if constexpr (SCB) zr *= zsc[t][q][r];
             __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, zr), rout, vo, so, 0);
           }
+        }
+      }
+  };
+  // the scale entries store_z(ps) multiplies by (same offsets)
+  auto load_scale = [&](const SlabPos& ps, int lane) {
+    const int g = lane >> 4, l16 = lane & 15;
+    auto& u = slab_unit(args, ps.ui);
+    const int n1 = u.n1, n2 = u.n2, n1p = n1 + (n1 & 1);
+    const uint32_t vlane = (uint32_t)(l16 + 4 * g * n1p) * 2;
+    const __amdgpu_buffer_rsrc_t rsc =
+        make_rsrc(static_cast<const S*>(u.scale) + (int64_t)n1p * n2 * ps.i3, (uint32_t)(n1p * n2) * 2);
+#pragma unroll
+    for (int t = 0; t < TB; ++t)
+#pragma unroll
+      for (int q = 0; q < TB; ++q) {
+        const int j2t = 16 * (wa * TB + t), j1t = 16 * (wb * TB + q);
+        const bool inner = wa * TB + t < MT && wb * TB + q < MT && j1t + 16 <= n1 && j2t + 16 <= n2;
+        const bool okl = wa * TB + t < MT && wb * TB + q < MT && l16 + j1t < n1;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const uint32_t so = (uint32_t)(j1t + n1p * (j2t + r)) * 2;
+          const uint32_t vo = inner || (okl && j2t + 4 * g + r < n2) ? vlane : kOOB;
+          zsc[t][q][r] = (float)__builtin_bit_cast(S, (unsigned short)__builtin_amdgcn_raw_buffer_load_b16(rsc, vo, so, 0));
         }
       }
   };
@@ -336,11 +388,16 @@ void fd_slab_kernel(const Src args) {
             uint32_t v;
             if constexpr (FWD) {
               fl2 x = __builtin_bit_cast(fl2, xa[k]);
-              if constexpr (SC) x *= sa[k];
               if (2 * lane + 1 == n1) x = fl2{x[1], 0.0f};  // the lone last entry
+              if constexpr (SC) x *= scale2(sa[k]);
               v = cvt2(x);
             } else {
               v = (xa[k][0] & 0xffffu) | (xp[k] << 16);
+              if constexpr (SCL) {
+                const int n1p = n1 + (n1 & 1);
+                if (r < n2 && 2 * lane < n1p)
+                  *reinterpret_cast<uint32_t*>(sci + 2 * (r * (n1p + 16) + 2 * lane)) = sa[k];
+              }
             }
             *reinterpret_cast<uint32_t*>(xs + ((lpart ^ (rsw(r) << 4)) + W * 64 * k)) = v;
           }
@@ -354,7 +411,7 @@ void fd_slab_kernel(const Src args) {
             uint32_t v;
             if constexpr (FWD) {
               fl2 x = {__builtin_bit_cast(float, xb0[k]), __builtin_bit_cast(float, xb1[k])};
-              if constexpr (SC) x *= fl2{sb0[k], sb1[k]};
+              if constexpr (SC) x *= scale2(sbp[k]);
               v = cvt2(x);
             } else {
               v = (xb0[k] & 0xffffu) | (xb1[k] << 16);
@@ -377,6 +434,7 @@ void fd_slab_kernel(const Src args) {
     if (prevp.valid) store_z(prevp, lane);
     nxt = slab_pos(args, tile + t_step, cur);
     if (nxt.valid && tile + t_step < t_end) prefetch(nxt, lane);
+    if constexpr (SCB) load_scale(cur, lane);
     slab_barrier();
 
     // Fragment reads: row 16 T + l16 (T uniform), chunk g of block s; the
@@ -457,6 +515,17 @@ void fd_slab_kernel(const Src args) {
       for (int q = 0; q < TB; ++q) {
         f4 z = acc[t][q];
         if constexpr (P == 3 || !FWD) z *= u.s_out;
+        if constexpr (SCL) {
+          // D^{-1/2} at (j1, j2) from the slab's LDS image (entries past
+          // the slab read clamped positions: their results are not stored)
+          const int SR = n1 + (n1 & 1) + 16;
+          const int j1 = 16 * (wb * TB + q) + l16, j1c = j1 < SR ? j1 : SR - 1;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int j2 = 16 * (wa * TB + t) + 4 * g + r, j2c = j2 < ROWS ? j2 : ROWS - 1;
+            z[r] *= (float)*reinterpret_cast<const S*>(sci + 2 * (j2c * SR + j1c));
+          }
+        }
         if constexpr (FWD) zh[t][q] = __builtin_convertvector(z, v4);
         else zf[t][q] = z;
       }
@@ -468,7 +537,7 @@ void fd_slab_kernel(const Src args) {
 template <int P, int MT, bool FWD, bool SC, class Src>
 static hipError_t launch_slab_m(const Src& args, hipStream_t stream) {
   auto kern = fd_slab_kernel<P, MT, FWD, SC, Src>;
-  const size_t smem = slab_lds_bytes(MT);
+  const size_t smem = slab_lds_bytes(MT) + (slab_scale_lds(FWD, SC, MT) ? slab_sci_bytes(MT) : 0);
   // once per process (thread-safe initialisation of a function-local static)
   static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
