@@ -773,8 +773,8 @@ static fd_status batch_build_staged(fd_batch_s* b) {
         auto& pl = plan_of[mt];
         pl.first = sm;
         pl.second = std::max(pl.second, u.n);
-        auto& tb = lam_of[mt];  // the unit's weighted eigenvalues in LDS (FP64)
-        tb = std::max(tb, sizeof(double) * size_t(u.n1 + u.A / u.n1 + u.n));
+        auto& tb = lam_of[mt];  // the unit's weighted eigenvalues in LDS (FP32)
+        tb = std::max(tb, sizeof(float) * size_t(u.n1 + u.A / u.n1 + u.n));
       }
       for (auto& [mt, D] : groups) {
         int64_t t = 0;

@@ -154,7 +154,7 @@ hipError_t launch_slab(const SlabArgs& args, int prec, int mt, hipStream_t strea
 hipError_t launch_slab_tab(const SlabTab& tab, int prec, int mt, bool fwd, bool sc, hipStream_t stream);
 
 // LDS bytes of the weighted-eigenvalue tables of a divide pass (w_0 d_0, w_1 d_1
-// and w_l d_l of every unit, FP64), placed after the pipeline ring.
+// and w_l d_l of every unit, FP32), placed after the pipeline ring.
 size_t lam_table_bytes(const PassArgs& args);
 
 // Storage/compute class of a plan: 0 = FP64 MFMA, 1 = FP32 MFMA,

@@ -240,7 +240,7 @@ size_t lam_table_bytes(const PassArgs& args) {
     const PassDesc& v = args.u[k];
     e += size_t(v.lam_ndim == 3 ? v.n1 + v.A / v.n1 : v.A) + size_t(v.n);
   }
-  return e * sizeof(double);
+  return e * sizeof(float);
 }
 
 size_t plain_bytes(int n, int prec) {
