@@ -321,6 +321,12 @@ fd_status fd_batch_tune(fd_batch batch, void* stream, int32_t reps, int32_t* cho
 fd_status fd_batch_set_config(fd_batch batch, int32_t config);
 /* Tiles per apply, grid size and configuration word. */
 fd_status fd_batch_info(fd_batch batch, int64_t* tiles, int32_t* grid, int32_t* config);
+/* A 64-bit signature of what the batch's layout and tuned configuration
+ * depend on (the device's CU count, the precision class and, per work, the
+ * plan's sizes, route and scaling and nrhs; not the buffers): batches with
+ * equal signatures may share a configuration word, so a caller can keep
+ * tuning results across processes (fd_batch_set_config). FD_E_ARG on NULL. */
+fd_status fd_batch_signature(fd_batch batch, uint64_t* sig);
 fd_status fd_batch_check(fd_batch batch);
 fd_status fd_batch_destroy(fd_batch batch);
 

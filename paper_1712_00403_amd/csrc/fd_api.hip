@@ -1665,6 +1665,34 @@ fd_status fd_batch_info(fd_batch b, int64_t* tiles, int32_t* grid, int32_t* conf
   return FD_OK;
 }
 
+fd_status fd_batch_signature(fd_batch b, uint64_t* sig) {
+  if (!b || !sig) return fail(FD_E_ARG, "fd_batch_signature: bad arguments");
+  // FNV-1a over what the layout and the tuned configuration depend on: the
+  // device's CU count, the precision class and per work the plan's shape,
+  // route, scaling and the number of residuals (not the buffers)
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&h](int64_t v) {
+    for (int i = 0; i < 8; ++i) {
+      h ^= uint64_t(v >> (8 * i)) & 0xffu;
+      h *= 1099511628211ull;
+    }
+  };
+  mix(b->cus);
+  mix(b->prec);
+  mix(int64_t(b->works.size()));
+  for (const fd_work& wk : b->works) {
+    const fd_plan_s* p = wk.plan;
+    mix(p->ndim);
+    for (int i = 0; i < 3; ++i) mix(p->n[i]);
+    mix(p->mass_only);
+    mix(p->slab);
+    mix(p->scale_dev != nullptr);
+    mix(wk.nrhs);
+  }
+  *sig = h;
+  return FD_OK;
+}
+
 fd_status fd_batch_check(fd_batch b) {
   if (!b) return fail(FD_E_ARG, "fd_batch_check: NULL batch");
   hipError_t e = hipDeviceSynchronize();

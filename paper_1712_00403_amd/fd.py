@@ -7,6 +7,7 @@ be built (``python -m paper_1712_00403_amd.build``); loading fails loudly
 otherwise, there is no fallback.
 """
 import ctypes
+import json
 import os
 
 import numpy as np
@@ -24,7 +25,7 @@ EXPORTS = ("fd_assemble_1d", "fd_nitsche_stiffness_1d", "fd_mixed_1d", "fd_quadr
            "fd_separable_factors", "fd_operator_diagonal", "fd_setup", "fd_setup_mass_banded", "fd_destroy",
            "fd_plan_size", "fd_plan_device_bytes", "fd_workspace_bytes", "fd_plan_factors", "fd_apply",
            "fd_apply_batched", "fd_batch_create", "fd_batch_apply", "fd_batch_tune", "fd_batch_set_config",
-           "fd_batch_info", "fd_batch_check", "fd_batch_destroy", "fd_apply_persistent_static", "fd_timing_enable", "fd_timing_read", "fd_timing_launches", "fd_last_error")
+           "fd_batch_info", "fd_batch_signature", "fd_batch_check", "fd_batch_destroy", "fd_apply_persistent_static", "fd_timing_enable", "fd_timing_read", "fd_timing_launches", "fd_last_error")
 
 
 class FDError(RuntimeError):
@@ -91,11 +92,12 @@ def lib():
     L.fd_batch_set_config.argtypes = [ctypes.c_void_p, ctypes.c_int32]
     L.fd_batch_set_config.restype = ctypes.c_int
     L.fd_batch_check.argtypes = [ctypes.c_void_p]
+    L.fd_batch_signature.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]
     L.fd_batch_destroy.argtypes = [ctypes.c_void_p]
     L.fd_apply_persistent_static.argtypes = [ctypes.c_int32, ctypes.POINTER(FDWork), ctypes.c_int32,
                                              ctypes.c_void_p, ctypes.c_void_p]
     for name in ("fd_batch_create", "fd_batch_apply", "fd_batch_tune", "fd_batch_info", "fd_batch_check",
-                 "fd_batch_destroy", "fd_apply_persistent_static"):
+                 "fd_batch_signature", "fd_batch_destroy", "fd_apply_persistent_static"):
         getattr(L, name).restype = ctypes.c_int
     L.fd_timing_enable.argtypes = [ctypes.c_int32]
     L.fd_timing_read.argtypes = [c_dp, ctypes.POINTER(ctypes.c_int32)]
@@ -406,12 +408,38 @@ class Batch:
     def choices_of(config):
         return [(int(config) >> (2 * s)) & 3 for s in range(5)]
 
-    def tune(self, stream=None, reps=3):
+    def tune(self, stream=None, reps=3, cache=None):
         """Choose the body of every stage by timing (greedy), then the staged route if the batch
-        has one and it is faster; returns the configuration word."""
+        has one and it is faster; returns the configuration word.
+
+        ``cache``: None, or the path of a JSON file of configuration words keyed by batch
+        signature: a batch whose signature is there takes that word without timing; otherwise
+        the tuned word is added to the file."""
+        key = None
+        table = {}
+        if cache is not None:
+            key = format(self.signature(), "016x")
+            if os.path.exists(cache):
+                with open(cache) as fh:
+                    table = json.load(fh)
+            if key in table:
+                self.set_config(int(table[key]))
+                return int(table[key])
         c = ctypes.c_int32(0)
         _check(lib().fd_batch_tune(self.handle, _stream_handle(stream), int(reps), ctypes.byref(c)))
+        if cache is not None:
+            table[key] = c.value
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as fh:
+                json.dump(table, fh, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
         return c.value
+
+    def signature(self):
+        """64-bit signature of the batch's layout (fd_batch_signature)."""
+        s = ctypes.c_uint64(0)
+        _check(lib().fd_batch_signature(self.handle, ctypes.byref(s)))
+        return s.value
 
     def set_config(self, config):
         _check(lib().fd_batch_set_config(self.handle, int(config)))

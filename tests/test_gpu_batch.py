@@ -249,6 +249,34 @@ def test_staged_route_availability():
             pc.close()
 
 
+def test_batch_signature_and_tuning_cache(tmp_path):
+    """Equal layouts give equal signatures whatever the buffers; a different nrhs or
+    precision changes it; tune(cache=...) stores the word and a second batch with the
+    same signature takes it from the file."""
+    _case("batch signature and tuning cache")
+    from paper_1712_00403_amd import fd
+    pcs, _ = _build("f32")
+    _, zs_a, works_a = _batch_io(pcs, STAGED_PATCHES, 1, 100, torch.float32)
+    _, zs_b, works_b = _batch_io(pcs, STAGED_PATCHES, 1, 110, torch.float32)
+    _, zs_c, works_c = _batch_io(pcs, STAGED_PATCHES, 2, 120, torch.float32)
+    a, b, c = fd.Batch(works_a), fd.Batch(works_b), fd.Batch(works_c)
+    assert a.signature() == b.signature() != c.signature()
+    cache = str(tmp_path / "tune.json")
+    cfg = a.tune(reps=1, cache=cache)
+    import json
+    with open(cache) as fh:
+        assert json.load(fh) == {format(a.signature(), "016x"): cfg}
+    b.set_config(0)
+    assert b.tune(reps=1, cache=cache) == cfg and b.info()["config"] == cfg
+    b.apply()
+    b.check()
+    torch.cuda.synchronize()
+    for x in (a, b, c):
+        x.close()
+    for pc in pcs:
+        pc.close()
+
+
 def test_persistent_batch_rejects_large_factors():
     _case("persistent batch argument checks")
     from paper_1712_00403_amd import fd
