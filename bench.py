@@ -413,14 +413,42 @@ def bench_small(args, precisions):
                 pc.apply(r, z)
             torch.cuda.synchronize()
             us = (time.perf_counter() - t0) * 1e6 / reps
+            # the same apply recorded once as a HIP graph and replayed
+            g = pc.graph(r, z)
+            for _ in range(args.warmup * 10):
+                g.replay()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                g.replay()
+            torch.cuda.synchronize()
+            us_graph = (time.perf_counter() - t0) * 1e6 / reps
+            del g
+            # the same works as one fixed batch (one persistent launch, or the staged route)
+            from paper_1712_00403_amd import fd as _fd
+            bt = _fd.Batch(pc.works(r.data_ptr(), z.data_ptr(), cfg["nrhs"]))
+            bt_cfg = bt.tune(reps=20)
+            for _ in range(args.warmup * 10):
+                bt.apply()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                bt.apply()
+            torch.cuda.synchronize()
+            us_batch = (time.perf_counter() - t0) * 1e6 / reps
+            bt.check()
+            bt.close()
             e = block_errors(z.double().cpu().numpy(), zo, pc.offsets)
             per = np.array(e["rel_err_per_residual"])
             leg["precisions"][p] = {"us_per_step": round(us, 2), "us_per_residual_apply": round(us / cfg["nrhs"], 3),
+                                    "us_per_step_graph_replay": round(us_graph, 2),
+                                    "us_per_step_fixed_batch": round(us_batch, 2), "fixed_batch_config": bt_cfg,
                                     "rel_err_max": e["rel_err_max"], "rel_maxnorm_err_max": e["rel_maxnorm_err_max"],
                                     "rel_err_per_residual_quantiles": {
                                         "min": float(per.min()), "p50": float(np.median(per)),
                                         "p90": float(np.percentile(per, 90)), "max": float(per.max())}}
-            log(f"2D 16^2 {name} {p}: {us:.1f} us per {cfg['nrhs']}-residual step, rel err max {e['rel_err_max']:.2e}")
+            log(f"2D 16^2 {name} {p}: {us:.1f} us per {cfg['nrhs']}-residual step ({us_graph:.1f} us as a graph "
+                f"replay, {us_batch:.1f} us as a fixed batch), rel err max {e['rel_err_max']:.2e}")
             pc.close()
         out["legs"][name] = leg
     return out

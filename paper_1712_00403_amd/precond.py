@@ -75,6 +75,29 @@ class BlockPreconditioner:
         fd.apply_batched(self.works(r.data_ptr(), z.data_ptr(), r2.shape[0]), stream)
         return z
 
+    def graph(self, r, z, warmup=2):
+        """A HIP graph of z = P_D^{-1} r on these two buffers; ``.replay()`` reruns it.
+
+        The launches of one apply are recorded once (on a side stream, after
+        ``warmup`` eager applies there), so a replay is one submission instead
+        of one per kernel: for small blocks the apply is launch-bound. The
+        apply records no memset or host synchronization, so its replays are
+        exact; r's contents may change between replays, its address may not.
+        """
+        import torch
+        dev = self.plans[0].device
+        fd.check_vectors(r, z, self.N, self.io_dtype, dev, exact=True)
+        side = torch.cuda.Stream(device=r.device)
+        side.wait_stream(torch.cuda.current_stream(r.device))
+        with torch.cuda.stream(side):
+            for _ in range(warmup):
+                self.apply(r, z, stream=side)
+        torch.cuda.current_stream(r.device).wait_stream(side)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            self.apply(r, z, stream=side)
+        return g
+
     def close(self):
         for p in self.plans:
             p.close()
