@@ -5,8 +5,9 @@
 //   P1: Y^T(i2, j1) = sum_i1 X(i1, i2) F1(j1, i1)   A = X, B = F1
 //   P2: Z^T(j2, j1) = sum_i2 F2(j2, i2) Y(j1, i2)   A = F2, B = Y
 // on 16x16x32 MFMA tiles with FP32 accumulation, every operand read from
-// LDS. One workgroup per CU keeps both factors in LDS for as long as its
-// slabs belong to one unit, and stages each slab in 16 bits (row i2 holds
+// LDS. A workgroup (one per CU at orders above 112, several below) keeps
+// both factors in LDS for as long as its slabs belong to one unit, and
+// stages each slab in 16 bits (row i2 holds
 // the i1 entries, P1's contraction index); P1's accumulators, converted to
 // 16 bits, become the rows j1 of Y with i2 contiguous (P2's contraction
 // index) in the same LDS image; P2's accumulators hold runs of 16
@@ -24,6 +25,12 @@
 // product, exactly as the pencil passes do at their fragment reads, so the
 // 16-bit layout between passes (SlabDesc) changes no result. FP16 plans scale
 // by powers of two (s_in, s_mid, s_out) to stay in range; BF16 plans use 1.
+// Coefficient-aware blocks scale by D^{-1/2} (Sec. 6), read in the 16-bit
+// type: the forward pass on load, the backward pass in its epilogue.
+//
+// Units come from the kernel arguments (up to kMaxDesc per launch, slabs
+// strided over the grid) or from a device table (fixed batches, a
+// contiguous range of slabs per workgroup).
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -176,9 +183,8 @@ void fd_slab_kernel(const Src args) {
 
   // The next slab's input is loaded into registers while the current slab
   // computes. FWD: xa holds the FP32 pair of a row (lane l: 2l, 2l + 1),
-  // xb0/xb1 the tail pair; sa, sb0/sb1 their D^{-1/2} entries. Backward:
-  // xa[.][0]/xp hold the two 16-bit entries of the pair, xb0/xb1 those of the
-  // tail pair.
+  // xb0/xb1 the tail pair. Backward: xa[.][0]/xp hold the two 16-bit entries
+  // of the pair, xb0/xb1 those of the tail pair.
   u32x2 xa[KA];
   uint32_t xp[FWD ? 1 : KA], xb0[KB], xb1[KB];
   // D^{-1/2} in 16 bits, rows of n1 + (n1 & 1) entries (SlabDesc::scale):
