@@ -346,7 +346,7 @@ def check_c4_samples(Z, offs, pcs, c4, prec, what):
 
 @pytest.mark.skipif(not os.path.exists(os.path.join(GOLDEN_DIR, "batch_256_sampled.npz")),
                     reason="stored oracle values not generated (tests/golden/make_batch_golden.py)")
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f16"])
 def test_c4_batch_256_patches_largest_and_drawn(prec):
     """The 256-patch batch in one persistent launch (default and tuned configurations, as timed by the bench).
 
@@ -382,7 +382,7 @@ def test_c4_batch_256_patches_largest_and_drawn(prec):
     torch.cuda.synchronize()
     e = check_c4_samples(Z.double().cpu().numpy(), offs, pcs, c4, prec, f"tuned config {cfg}")
     print(f"  tuned config {cfg}: sampled rel err {e[0]:.3e}, rel max err {e[1]:.3e}")
-    if prec == "bf16":  # the staged route (every patch is a slab-route plan)
+    if prec in ("bf16", "f16"):  # the staged route (every patch is a slab-route plan)
         batch.set_config(fd.Batch.STAGED)
         Z.fill_(float("nan"))
         batch.apply()

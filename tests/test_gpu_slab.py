@@ -158,6 +158,40 @@ def test_slab_nonfinite_residual_stays_isolated(prec):
     plan.close()
 
 
+# scaled blocks (Sec. 6: z = D^{-1/2} P^{-1} D^{-1/2} r): the backward pass
+# stages D^{-1/2} in LDS for orders up to 112 and loads it a slab ahead into
+# registers above; the forward pass reads the columns past 128 separately
+SCALED_CASES = [
+    ((50, 7, 3), 3),   # n = (101, 15, 7): D^{-1/2} through LDS
+    ((60, 4, 3), 3),   # (121, 9, 7): registers one slab ahead
+    ((64, 10, 3), 3),  # (129, 21, 7): registers, columns past 128, odd rows
+    ((4, 64, 3), 3),   # (9, 129, 7)
+]
+
+
+@pytest.mark.parametrize("prec", ["bf16", "f16"])
+@pytest.mark.parametrize("n_el,p", SCALED_CASES)
+def test_slab_scaled_matches_oracle(prec, n_el, p):
+    _case(f"slab route with D^-1/2, n_el={n_el} p={p} prec={prec}")
+    Ks, Ms = _vel(n_el, p)
+    w = np.array([1.0, 2.0, 1.0])
+    f = FDFactors(Ks, Ms, w)
+    N = int(np.prod(f.n))
+    dK = [np.diag(K) for K in Ks]
+    dM = [np.diag(M) for M in Ms]
+    diagP = (w[2] * np.einsum("k,j,i->kji", dK[2], dM[1], dM[0]) + w[1] * np.einsum("k,j,i->kji", dM[2], dK[1], dM[0])
+             + w[0] * np.einsum("k,j,i->kji", dM[2], dM[1], dK[0])).reshape(-1)
+    D = 0.5 + np.random.default_rng(36).random(N)
+    plan = _fd().Plan(Ks, Ms, weights=w, diag_target=diagP * D, precision=prec)
+    r = workloads.residuals(37, 2, plan.N)
+    z, fams = _apply(plan, r, timing=True)
+    assert fams.get("mode1_fwd") == {SLAB_FAMILY} and fams.get("mode1_bwd") == {SLAB_FAMILY}, fams
+    s = 1.0 / np.sqrt(D)
+    for j in range(2):
+        check_close(z[j], s * fd_apply(f, s * r[j]), prec, f"residual {j}")
+    plan.close()
+
+
 @pytest.mark.parametrize("prec", ["bf16", "f16"])
 def test_slab_order_limit(prec):
     """n1 = 145 is past the slab kernel (144): the plan takes the five-stage route, still correct."""
