@@ -92,6 +92,7 @@ struct fd_batch_s {
     int stage;        // 0, 2 or 4
     int mt;           // slab: row tiles of max(n1, n2); fused: of the last order
     bool sc;          // slab: the units scale by D^{-1/2}; fused: eigenvalue tables in LDS
+    bool walk;        // fused: units one by one over contiguous tile ranges (else tiles strided)
     size_t off;       // byte offset of the units (SlabDesc or BatchDesc) in sdev
     int count;        // units
     int64_t tiles;
@@ -785,8 +786,8 @@ static fd_status batch_build_staged(fd_batch_s* b) {
         if (t > 0x7fffffffLL) return fail(FD_E_ARG, "fd_batch_create: too many tiles in one launch");
         // the eigenvalue tables sit after the ring when they fit the LDS
         const bool lam = plan_of[mt].first + lam_of[mt] <= 160 * 1024;
-        fd_batch_s::StagedLaunch L{2, mt, lam, put(D.data(), D.size() * sizeof(fdk::BatchDesc)), int(D.size()),
-                                   t, plan_of[mt].first + (lam ? lam_of[mt] : 0), plan_of[mt].second};
+        fd_batch_s::StagedLaunch L{2, mt, lam, lam, put(D.data(), D.size() * sizeof(fdk::BatchDesc)),
+                                   int(D.size()), t, plan_of[mt].first + (lam ? lam_of[mt] : 0), plan_of[mt].second};
         b->staged.push_back(L);
       }
     } else {
@@ -806,8 +807,8 @@ static fd_status batch_build_staged(fd_batch_s* b) {
           max_n = std::max(max_n, std::max(d.n1, d.n2));
         }
         if (t > 0x7fffffffLL) return fail(FD_E_ARG, "fd_batch_create: too many tiles in one launch");
-        fd_batch_s::StagedLaunch L{stage, key.first, key.second == 1, put(D.data(), D.size() * sizeof(fdk::SlabDesc)),
-                                   int(D.size()), t, 0, max_n};
+        fd_batch_s::StagedLaunch L{stage, key.first, key.second == 1, false,
+                                   put(D.data(), D.size() * sizeof(fdk::SlabDesc)), int(D.size()), t, 0, max_n};
         b->staged.push_back(L);
       }
     }
@@ -835,7 +836,7 @@ static hipError_t staged_launch_one(fd_batch_s* b, const fd_batch_s::StagedLaunc
     sg.mode = 2;
     sg.mt = L.mt;
     sg.scale = L.sc ? 1 : 0;  // (fused launches: the eigenvalue tables go to LDS)
-    sg.body = fdk::kBodyPipelined;
+    sg.body = L.walk ? 1 : 0;
     return fdk::launch_seg3(reinterpret_cast<const fdk::BatchDesc*>(base), sg, cls, L.mt, L.smem, stream);
   }
   fdk::SlabTab t{reinterpret_cast<const fdk::SlabDesc*>(base), L.count, int(L.tiles)};
@@ -1618,11 +1619,28 @@ fd_status fd_batch_tune(fd_batch b, void* stream, int32_t reps, int32_t* choice)
     b->width[stage] = keep;
   }
   if (s == FD_OK) s = batch_upload(b);
-  // the staged route, where the batch has one
+  // the staged route, where the batch has one: first per fused launch the
+  // faster of unit-by-unit (eigenvalues in LDS) and strided tiles, timed
+  // alone, then the route as a whole against the persistent launch
   if (s == FD_OK && !b->staged.empty()) {
+    for (auto& L : b->staged) {
+      if (L.stage != 2 || !L.sc || s != FD_OK) continue;
+      float t_mode[2] = {0.0f, 0.0f};
+      for (int m = 0; m < 2 && s == FD_OK; ++m) {
+        L.walk = m == 1;
+        hipError_t er = staged_launch_one(b, L, st);  // warm-up
+        if (er == hipSuccess) er = hipEventRecord(e0, st);
+        for (int r = 0; r < reps && er == hipSuccess; ++r) er = staged_launch_one(b, L, st);
+        if (er == hipSuccess) er = hipEventRecord(e1, st);
+        if (er == hipSuccess) er = hipEventSynchronize(e1);
+        if (er == hipSuccess) er = hipEventElapsedTime(&t_mode[m], e0, e1);
+        if (er != hipSuccess) s = hip_fail(er, "fd_batch_tune");
+      }
+      L.walk = t_mode[1] <= t_mode[0];
+    }
     b->use_staged = true;
     float ms = 0.0f;
-    s = time_current(&ms);
+    if (s == FD_OK) s = time_current(&ms);
     b->use_staged = s == FD_OK && ms < best;
   }
   (void)hipEventDestroy(e0);
