@@ -316,8 +316,12 @@ fd_status fd_batch_create(int32_t count, const fd_work* work, fd_batch* out);
 fd_status fd_batch_apply(fd_batch batch, void* stream);
 fd_status fd_batch_tune(fd_batch batch, void* stream, int32_t reps, int32_t* choice);
 /* Sets the body choices directly (a configuration word, e.g. from an earlier
- * tune; a choice of 3 is FD_E_ARG; 1 << 10 selects the staged route);
- * synchronizes the device. */
+ * tune; a choice of 3 is FD_E_ARG; 1 << 10 selects the staged route; bit 11
+ * with body choices selects the segment route: every segment of the
+ * persistent layout as a launch of its own with its own LDS size, in stage
+ * order on the stream, bit-identical results, no grid barrier and hence no
+ * co-residency requirement); synchronizes the device. fd_batch_tune also
+ * times the segment route with the chosen bodies and keeps it if faster. */
 fd_status fd_batch_set_config(fd_batch batch, int32_t config);
 /* Tiles per apply, grid size and configuration word. */
 fd_status fd_batch_info(fd_batch batch, int64_t* tiles, int32_t* grid, int32_t* config);

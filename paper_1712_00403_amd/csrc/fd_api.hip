@@ -68,6 +68,7 @@ struct fd_batch_s {
   struct Layout {
     std::vector<fdk::BatchDesc> desc[5];
     std::vector<fdk::BatchSeg> seg[5];
+    std::vector<size_t> seg_smem[5];  // LDS bytes of each segment's body (segment route)
     int64_t tiles[5] = {0, 0, 0, 0, 0};
     bool differs[5] = {false, false, false, false, false};  // some pass of the stage runs another body than wide
   } lay[3];
@@ -80,6 +81,12 @@ struct fd_batch_s {
   void* dev = nullptr;    // descriptors and segments of the current widths
   size_t dev_cap = 0;
   void* ctl = nullptr;    // barrier counter and error flag
+  // segment route (configuration bit kBatchSegments): every segment of the
+  // uploaded tables as a launch of its own, in stage order; per uploaded
+  // segment its LDS bytes and grid
+  bool use_segments = false;
+  std::vector<size_t> up_smem;
+  std::vector<int> up_grid;
   uint32_t arrivals = 0;  // barrier arrivals counted so far
   int cus = 0;
   bool tuned = false;
@@ -593,6 +600,7 @@ static fd_status batch_build_layout(fd_batch_s* b, int choice) {
     L.differs[stage] = false;
     // passes of this stage, grouped by body (kind, mode, row tiles, scaling)
     std::vector<std::pair<int, fdk::BatchDesc>> passes;  // (body, descriptor)
+    std::vector<size_t> pass_smem;
     for (const fd_work& wk : b->works) {
       int body = 0;
       fdk::BatchDesc bd;
@@ -601,16 +609,31 @@ static fd_status batch_build_layout(fd_batch_s* b, int choice) {
       b->smem = std::max(b->smem, sm);
       if (body != fdk::kBodyWide) L.differs[stage] = true;
       passes.emplace_back(body, bd);
+      pass_smem.push_back(sm);
     }
     // segments of a stage run one after another on every workgroup: the
     // largest row-tile counts first, so that the tiles left when workgroups
     // reach the stage's barrier are the cheapest ones
     auto key = [](const std::pair<int, fdk::BatchDesc>& x) { return batch_key(x.first, x.second); };
-    std::stable_sort(passes.begin(), passes.end(), [&](const auto& x, const auto& y) { return key(x) < key(y); });
+    std::vector<size_t> order(passes.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return key(passes[x]) < key(passes[y]); });
+    {
+      std::vector<std::pair<int, fdk::BatchDesc>> sorted;
+      std::vector<size_t> sorted_smem;
+      for (size_t i : order) {
+        sorted.push_back(passes[i]);
+        sorted_smem.push_back(pass_smem[i]);
+      }
+      passes.swap(sorted);
+      pass_smem.swap(sorted_smem);
+    }
+    L.seg_smem[stage].clear();
     int64_t t = 0;
     for (size_t i = 0; i < passes.size(); ++i) {
       fdk::BatchDesc bd = passes[i].second;
       if (i == 0 || key(passes[i - 1]) != key(passes[i])) {
+        L.seg_smem[stage].push_back(0);
         fdk::BatchSeg sg{};
         sg.d0 = int(D.size());
         sg.t0 = int(t);
@@ -623,6 +646,7 @@ static fd_status batch_build_layout(fd_batch_s* b, int choice) {
       bd.u.tile_begin = t;
       t += int64_t(bd.u.tiles_per_rhs) * bd.u.nrhs;
       if (t > 0x7fffffffLL) return fail(FD_E_ARG, "fd_batch_create: too many tiles in one stage");
+      L.seg_smem[stage].back() = std::max(L.seg_smem[stage].back(), pass_smem[i]);
       D.push_back(bd);
       S.back().d1 = int(D.size());
       S.back().t1 = int(t);
@@ -637,14 +661,24 @@ static fd_status batch_upload(fd_batch_s* b) {
   std::vector<fdk::BatchDesc> desc;
   std::vector<fdk::BatchSeg> seg;
   b->max_tiles = 0;
+  b->up_smem.clear();
+  b->up_grid.clear();
   for (int st = 0; st < kStages; ++st) {
     const auto& L = b->lay[b->width[st]];
     b->stage_seg[st] = int(seg.size());
     const int base = int(desc.size());
-    for (fdk::BatchSeg sg : L.seg[st]) {
+    for (size_t k = 0; k < L.seg[st].size(); ++k) {
+      fdk::BatchSeg sg = L.seg[st][k];
       sg.d0 += base;
       sg.d1 += base;
       seg.push_back(sg);
+      // the segment route's launch: its own LDS, as many workgroups as fit
+      const size_t sm = L.seg_smem[st][k];
+      int per_cu = 0;
+      hipError_t e = fdk::batch_seg_resident(b->prec, sm, &per_cu);
+      if (e != hipSuccess) return hip_fail(e, "batch occupancy");
+      b->up_smem.push_back(sm);
+      b->up_grid.push_back(int(std::min<int64_t>(int64_t(b->cus) * std::max(per_cu, 1), sg.t1 - sg.t0)));
     }
     desc.insert(desc.end(), L.desc[st].begin(), L.desc[st].end());
     b->max_tiles = std::max(b->max_tiles, L.tiles[st]);
@@ -672,6 +706,19 @@ static fd_status batch_launch_staged(fd_batch_s* b, hipStream_t stream);
 static fd_status batch_launch(fd_batch_s* b, hipStream_t stream) {
   if (b->use_staged) return batch_launch_staged(b, stream);
   if (b->max_tiles == 0) return FD_OK;
+  if (b->use_segments) {
+    fdk::BatchArgs a{};
+    size_t nd = 0;
+    for (int st = 0; st < kStages; ++st) nd += b->lay[b->width[st]].desc[st].size();
+    unsigned char* base = static_cast<unsigned char*>(b->dev);
+    a.desc = reinterpret_cast<const fdk::BatchDesc*>(base);
+    a.seg = reinterpret_cast<const fdk::BatchSeg*>(base + nd * sizeof(fdk::BatchDesc));
+    for (int k = 0; k < b->stage_seg[kStages]; ++k) {
+      hipError_t e = fdk::batch_seg_launch(a, b->prec, k, b->up_grid[size_t(k)], b->up_smem[size_t(k)], stream);
+      if (e != hipSuccess) return hip_fail(e, "batch segment launch");
+    }
+    return FD_OK;
+  }
   // one 8-wavefront workgroup per CU: the pass bodies are called functions
   // with a stack, and the scratch the runtime grants is sized for that
   const int64_t grid = std::min<int64_t>(b->cus, b->max_tiles);
@@ -719,16 +766,17 @@ static fd_status batch_validate(int32_t count, const fd_work* work, const char* 
   return FD_OK;
 }
 
-// Configuration word of the staged route (beyond the ten bits of the
-// persistent body choices).
+// Configuration words beyond the ten bits of the body choices: the staged
+// route, and the segment route (with the body choices of its segments).
 constexpr int kBatchStaged = 1 << 10;
+constexpr int kBatchSegments = 1 << 11;
 
 // two bits per stage: the body choice of stage s in bits 2s, 2s + 1
 static int batch_config(const fd_batch_s* b) {
   if (b->use_staged) return kBatchStaged;
   int c = 0;
   for (int st = 0; st < kStages; ++st) c |= b->width[st] << (2 * st);
-  return c;
+  return c | (b->use_segments ? kBatchSegments : 0);
 }
 
 // Lays out and uploads the staged route when every work with residuals is a
@@ -1599,6 +1647,7 @@ fd_status fd_batch_tune(fd_batch b, void* stream, int32_t reps, int32_t* choice)
   // greedy over stages: each stage keeps the body choice that made the whole
   // apply fastest, given the choices already made for the earlier stages
   b->use_staged = false;
+  b->use_segments = false;
   for (int i = 0; i < kStages; ++i) b->width[i] = 0;
   fd_status s = batch_upload(b);
   float best = 0.0f;
@@ -1619,6 +1668,14 @@ fd_status fd_batch_tune(fd_batch b, void* stream, int32_t reps, int32_t* choice)
     b->width[stage] = keep;
   }
   if (s == FD_OK) s = batch_upload(b);
+  // the segment route with the chosen bodies
+  if (s == FD_OK) {
+    b->use_segments = true;
+    float ms = 0.0f;
+    s = time_current(&ms);
+    if (s == FD_OK && ms < best) best = ms;
+    else b->use_segments = false;
+  }
   // the staged route, where the batch has one: first per fused launch the
   // faster of unit-by-unit (eigenvalues in LDS) and strided tiles, timed
   // alone, then the route as a whole against the persistent launch
@@ -1660,8 +1717,11 @@ fd_status fd_batch_set_config(fd_batch b, int32_t config) {
     b->use_staged = true;
     return FD_OK;
   }
-  if (!b || config < 0 || config >= (1 << (2 * kStages))) return fail(FD_E_ARG, "fd_batch_set_config: bad arguments");
+  if (!b || config < 0 || (config & ~kBatchSegments) >= (1 << (2 * kStages)))
+    return fail(FD_E_ARG, "fd_batch_set_config: bad arguments");
   b->use_staged = false;
+  b->use_segments = (config & kBatchSegments) != 0;
+  config &= ~kBatchSegments;
   for (int st = 0; st < kStages; ++st)
     if (((config >> (2 * st)) & 3) == 3) return fail(FD_E_ARG, "fd_batch_set_config: body choice 3");
   for (int st = 0; st < kStages; ++st) b->width[st] = (config >> (2 * st)) & 3;

@@ -6,4 +6,6 @@
 namespace fdk {
 template hipError_t batch_launch_p<4>(const BatchArgs&, int, size_t, hipStream_t);
 template hipError_t batch_resident_p<4>(size_t, int*);
+template hipError_t batch_seg_launch_p<4>(const BatchArgs&, int, int, size_t, hipStream_t);
+template hipError_t batch_seg_resident_p<4>(size_t, int*);
 }  // namespace fdk

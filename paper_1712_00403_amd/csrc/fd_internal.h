@@ -198,6 +198,10 @@ size_t batch_lds_bytes(int prec, int n, bool fused);
 hipError_t batch_resident(int prec, size_t smem, int* per_cu);
 hipError_t batch_launch(const BatchArgs& args, int prec, int grid, size_t smem, hipStream_t stream);
 hipError_t batch_reset(uint32_t* barrier, int32_t* error, hipStream_t stream);
+// The segment route: segment k of the batch's tables as one launch of its own
+// (args.desc, args.seg as the persistent launch; barrier fields unused).
+hipError_t batch_seg_launch(const BatchArgs& args, int prec, int k, int grid, size_t smem, hipStream_t stream);
+hipError_t batch_seg_resident(int prec, size_t smem, int* per_cu);
 
 // ---- banded Cholesky solves of the pressure-mass block (fd_banded.hip)
 struct BandDesc {

@@ -201,6 +201,43 @@ hipError_t batch_resident(int prec, size_t smem, int* per_cu) {
   }
 }
 
+template <int P> hipError_t batch_seg_launch_p(const BatchArgs&, int, int, size_t, hipStream_t);
+template <int P> hipError_t batch_seg_resident_p(size_t, int*);
+extern template hipError_t batch_seg_launch_p<0>(const BatchArgs&, int, int, size_t, hipStream_t);
+extern template hipError_t batch_seg_launch_p<1>(const BatchArgs&, int, int, size_t, hipStream_t);
+extern template hipError_t batch_seg_launch_p<2>(const BatchArgs&, int, int, size_t, hipStream_t);
+extern template hipError_t batch_seg_launch_p<3>(const BatchArgs&, int, int, size_t, hipStream_t);
+extern template hipError_t batch_seg_launch_p<4>(const BatchArgs&, int, int, size_t, hipStream_t);
+extern template hipError_t batch_seg_launch_p<5>(const BatchArgs&, int, int, size_t, hipStream_t);
+extern template hipError_t batch_seg_resident_p<0>(size_t, int*);
+extern template hipError_t batch_seg_resident_p<1>(size_t, int*);
+extern template hipError_t batch_seg_resident_p<2>(size_t, int*);
+extern template hipError_t batch_seg_resident_p<3>(size_t, int*);
+extern template hipError_t batch_seg_resident_p<4>(size_t, int*);
+extern template hipError_t batch_seg_resident_p<5>(size_t, int*);
+
+hipError_t batch_seg_launch(const BatchArgs& args, int prec, int k, int grid, size_t smem, hipStream_t stream) {
+  switch (prec) {
+    case 0: return batch_seg_launch_p<0>(args, k, grid, smem, stream);
+    case 1: return batch_seg_launch_p<1>(args, k, grid, smem, stream);
+    case 2: return batch_seg_launch_p<2>(args, k, grid, smem, stream);
+    case 3: return batch_seg_launch_p<3>(args, k, grid, smem, stream);
+    case 4: return batch_seg_launch_p<4>(args, k, grid, smem, stream);
+    default: return batch_seg_launch_p<5>(args, k, grid, smem, stream);
+  }
+}
+
+hipError_t batch_seg_resident(int prec, size_t smem, int* per_cu) {
+  switch (prec) {
+    case 0: return batch_seg_resident_p<0>(smem, per_cu);
+    case 1: return batch_seg_resident_p<1>(smem, per_cu);
+    case 2: return batch_seg_resident_p<2>(smem, per_cu);
+    case 3: return batch_seg_resident_p<3>(smem, per_cu);
+    case 4: return batch_seg_resident_p<4>(smem, per_cu);
+    default: return batch_seg_resident_p<5>(smem, per_cu);
+  }
+}
+
 extern template hipError_t launch_seg3_p<7>(const BatchDesc*, const BatchSeg&, int, size_t, hipStream_t);
 extern template hipError_t launch_seg3_p<8>(const BatchDesc*, const BatchSeg&, int, size_t, hipStream_t);
 

@@ -398,6 +398,9 @@ class Batch:
     # configuration word of the staged route (every work a 3D BF16/FP16
     # slab-route plan): one launch per stage and row-tile group
     STAGED = 1 << 10
+    # configuration bit of the segment route: every segment of the persistent
+    # layout (with the body choices of bits 0-9) as a launch of its own
+    SEGMENTS = 1 << 11
 
     @staticmethod
     def config_of(choices):

@@ -73,10 +73,15 @@ ALL_PIPELINED = 0b1010101010
 MIXED = 0b0110011000  # stages 0..4: wide, pipelined, narrow, pipelined, narrow
 
 
+SEGMENTS = 1 << 11  # the segment route
+
+
 @pytest.mark.parametrize("prec,config", [("f64", 0), ("f32", 0), ("bf16", 0), ("f16", 0), ("bf16_split", 0),
                                          ("f32", ALL_NARROW), ("bf16", ALL_NARROW), ("f64", MIXED),
                                          ("f64", ALL_PIPELINED), ("f32", ALL_PIPELINED), ("bf16", ALL_PIPELINED),
-                                         ("f16", ALL_PIPELINED), ("bf16_split", ALL_PIPELINED), ("f32", MIXED)])
+                                         ("f16", ALL_PIPELINED), ("bf16_split", ALL_PIPELINED), ("f32", MIXED),
+                                         ("f64", MIXED | SEGMENTS), ("f32", ALL_PIPELINED | SEGMENTS),
+                                         ("bf16", SEGMENTS), ("f16_split", ALL_NARROW | SEGMENTS)])
 def test_persistent_batch_matches_oracle(prec, config):
     _case(f"persistent batch of {len(PATCHES)} heterogeneous patches, prec={prec}, config={config}")
     from paper_1712_00403_amd import fd
@@ -131,7 +136,7 @@ def test_persistent_batch_tuning_keeps_results():
     batch = fd.Batch(works)
     choice = batch.tune(reps=2)
     assert batch.info()["config"] == choice
-    assert 0 <= choice < 1024 and all(c < 3 for c in fd.Batch.choices_of(choice))
+    assert 0 <= (choice & ~fd.Batch.SEGMENTS) < 1024 and all(c < 3 for c in fd.Batch.choices_of(choice))
     batch.apply()
     batch.check()
     torch.cuda.synchronize()
@@ -273,6 +278,33 @@ def test_batch_signature_and_tuning_cache(tmp_path):
     torch.cuda.synchronize()
     for x in (a, b, c):
         x.close()
+    for pc in pcs:
+        pc.close()
+
+
+@pytest.mark.parametrize("prec,config", [("f64", MIXED), ("f32", ALL_PIPELINED), ("bf16", 0)])
+def test_segment_route_equals_persistent_route(prec, config):
+    """The segment route runs the same bodies on the same tiles as the persistent
+    launch, one launch per segment: the results agree bit for bit."""
+    _case(f"segment route vs persistent launch, prec={prec}, config={config}")
+    from paper_1712_00403_amd import fd
+    pcs, _ = _build(prec)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    _, zs, works = _batch_io(pcs, range(len(PATCHES)), 2, 130, dt)
+    batch = fd.Batch(works)
+    outs = []
+    for cfg in (config, config | fd.Batch.SEGMENTS):
+        batch.set_config(cfg)
+        assert batch.info()["config"] == cfg
+        for _, zt in zs:
+            zt.fill_(float("nan"))
+        batch.apply()
+        batch.check()
+        torch.cuda.synchronize()
+        outs.append([zt.cpu().numpy() for _, zt in zs])
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b), "segment route differs from the persistent launch"
+    batch.close()
     for pc in pcs:
         pc.close()
 
