@@ -18,7 +18,10 @@ class (a Taylor-Hood patch in a precision). The server
   next step of their lane; small classes in a lane of their own never queue
   behind the steps of large ones;
 * records the completion of each step with an event on its lane's stream,
-  so the latency of a request is completion time minus arrival time.
+  so the latency of a request is completion time minus arrival time;
+* optionally sheds load: with ``max_wait`` set, a request still queued that
+  many seconds after its arrival is rejected (``Request.rejected``, listed
+  in ``Server.rejected``) instead of being served late.
 
 The executor is pluggable: ``GpuExecutor`` runs the library on HIP streams;
 tests drive the same scheduler with a CPU executor.
@@ -48,6 +51,7 @@ class Request:
     slot: int = 0                  # residual pool slot
     done: Optional[float] = None   # completion time on the server clock
     dofs: int = 0
+    rejected: bool = False         # shed after waiting longer than the server's max_wait
 
 
 class PlanCache:
@@ -110,8 +114,10 @@ class Server:
     """Continuous-batching scheduler with one FIFO per lane; the executor runs the steps."""
 
     def __init__(self, classes: Dict[str, RequestClass], executor, hbm_budget: int, max_step_dofs: int = 1 << 28,
-                 max_inflight: int = 2):
+                 max_inflight: int = 2, max_wait: Optional[float] = None):
         self.max_inflight = int(max_inflight)
+        self.max_wait = None if max_wait is None else float(max_wait)
+        self.rejected: List[Request] = []
         self.classes = classes
         self.ex = executor
         self.cache = PlanCache(executor.build, hbm_budget)
@@ -134,13 +140,32 @@ class Server:
     def _inflight_io(self):
         return sum(io for _, _, io, _ in self.inflight)
 
-    def step(self):
-        """Launch at most one step per lane from its admitted pending requests; returns the number launched."""
+    def step(self, now: Optional[float] = None):
+        """Launch at most one step per lane from its admitted pending requests; returns the number launched.
+
+        ``now`` (server seconds) is needed only with ``max_wait``: queued
+        requests that arrived more than ``max_wait`` before it are rejected first.
+        """
         self.collect()
+        if self.max_wait is not None and now is not None:
+            self._shed(now)
         launched = 0
         for lane in self.lanes:
             launched += self._step_lane(lane)
         return launched
+
+    def _shed(self, now):
+        for lane, q in self.queues.items():
+            if not any(now - r.arrival > self.max_wait for r in q):
+                continue
+            keep = collections.deque()
+            for r in q:
+                if now - r.arrival > self.max_wait:
+                    r.rejected = True
+                    self.rejected.append(r)
+                else:
+                    keep.append(r)
+            self.queues[lane] = keep
 
     def _step_lane(self, lane):
         q = self.queues[lane]
@@ -231,7 +256,7 @@ def run_stream(server: Server, arrivals, clock, pool_slots: Dict[str, int], idle
             reqs.append(r)
             server.submit(r)
             i += 1
-        launched = server.step()
+        launched = server.step(clock())
         if not launched:
             server.collect()
             if i < len(arrivals) and not server.pending:
@@ -252,7 +277,7 @@ def latency_summary(reqs, duration):
     for r in reqs:
         if r.done is not None:
             by_cls[r.cls].append(r.done - r.arrival)
-    return {"requests": int(lat.size), "p50_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
+    return {"requests": int(lat.size), "rejected": sum(1 for r in reqs if r.rejected), "p50_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
             "p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None,
             "dof_per_s": dofs / max(span, 1e-9),
             "per_class": {k: {"n": len(v), "p50_ms": float(np.percentile(v, 50) * 1e3),

@@ -185,3 +185,60 @@ def test_poisson_arrivals_rate_and_mix():
     frac = {k: sum(1 for _, c in arr if c == k) / len(arr) for k in "xyz"}
     assert abs(frac["x"] - 0.7) < 0.03 and abs(frac["z"] - 0.05) < 0.01
     assert serve.poisson_arrivals(2000.0, 5.0, {"x": 0.7, "y": 0.25, "z": 0.05}, seed=4) == arr
+
+
+def test_requests_waiting_past_max_wait_are_rejected():
+    # b (600 B plan) cannot be admitted while a's 2-s step (400 B plan, 400 B of
+    # results) is in flight; with max_wait 0.5 s, b's request of t = 0 is shed at
+    # t = 1, a later one is served
+    ex = VirtualExecutor({"a": 100, "b": 10}, {"a": 400, "b": 600}, base=0.0, per_dof=0.02)
+    srv = serve.Server(_classes(["a", "b"]), ex, hbm_budget=900, max_inflight=1, max_wait=0.5)
+    srv.submit(serve.Request(0, "a", 0.0))
+    assert srv.step(0.0) == 1
+    srv.submit(serve.Request(1, "b", 0.0))
+    assert srv.step(0.3) == 0 and not srv.rejected
+    ex.now = 1.0
+    srv.submit(serve.Request(2, "b", 0.9))
+    assert srv.step(1.0) == 0  # a's step (2 s) is still on the device
+    assert [r.rid for r in srv.rejected] == [1] and srv.rejected[0].rejected
+    ex.now = 2.0
+    srv.collect()
+    assert srv.step(1.2) == 1  # request 2 has waited 0.3 s: admitted
+    srv.collect(wait=True)
+    assert sorted(r.rid for r in srv.done) == [0, 2]
+    assert all(r.done is None for r in srv.rejected)
+
+
+def test_no_request_is_rejected_without_max_wait():
+    ex = VirtualExecutor({"a": 100, "b": 10}, {"a": 400, "b": 600}, base=0.0, per_dof=0.02)
+    srv = serve.Server(_classes(["a", "b"]), ex, hbm_budget=900, max_inflight=1)
+    srv.submit(serve.Request(0, "a", 0.0))
+    srv.submit(serve.Request(1, "b", 0.0))
+    for t in (0.0, 5.0, 50.0):
+        srv.step(t)
+    assert not srv.rejected
+    ex.now = 100.0
+    while srv.pending or srv.inflight:
+        srv.step(100.0)
+        srv.collect(wait=True)
+    assert sorted(r.rid for r in srv.done) == [0, 1]
+
+
+def test_run_stream_sheds_and_reports_rejections():
+    # one slow class on one lane, arrivals faster than it is served: with
+    # max_wait the stream ends with rejections counted in the summary
+    ex = VirtualExecutor({"a": 10}, {"a": 10}, base=0.05, per_dof=0.0)
+    clock_t = [0.0]
+
+    def clock():
+        clock_t[0] += 0.01
+        ex.now = clock_t[0]
+        return clock_t[0]
+
+    srv = serve.Server(_classes(["a"]), ex, hbm_budget=10 ** 6, max_inflight=1, max_step_dofs=10, max_wait=0.1)
+    arrivals = [(0.02 * i, "a") for i in range(50)]
+    reqs = serve.run_stream(srv, arrivals, clock, {"a": 1}, idle_sleep=0)
+    summ = serve.latency_summary(reqs, 1.0)
+    assert summ["rejected"] == len(srv.rejected) > 0
+    assert summ["requests"] + summ["rejected"] == len(arrivals)
+    assert max(r.done - r.arrival for r in reqs if r.done is not None) <= 0.1 + 0.05 + 0.02
