@@ -242,6 +242,19 @@ fd_status fd_setup_mass_banded(int32_t ndim, const int32_t* n, const double* con
 /* Plan queries: N = prod(n); device bytes held by the plan. */
 int64_t fd_plan_size(fd_plan plan);
 size_t fd_plan_device_bytes(fd_plan plan);
+
+/* Device-memory cap, for callers that budget HBM (a plan cache under a
+ * budget, a service sharing the GPU): the device bytes the library holds at
+ * once (plans, fixed-batch tables, setup temporaries; never the caller's r
+ * and z) stay at or below `bytes`; 0 removes the cap (the default). An
+ * fd_setup, fd_setup_mass_banded or fd_batch_create whose allocation would
+ * pass the cap fails with FD_E_NOMEM, exactly as on an exhausted device, and
+ * holds nothing afterwards. Lowering the cap below what is held frees
+ * nothing; it refuses later allocations. Process-wide (all devices,
+ * all threads). Always FD_OK. */
+fd_status fd_set_device_limit(size_t bytes);
+/* Device bytes the library holds now, the quantity the cap bounds. */
+size_t fd_device_bytes_held(void);
 /* Device workspace an apply of `nrhs` vectors needs beyond the plan and the
  * caller's r and z: 0. The first pass reads r and writes z, every later pass
  * of Algorithm 1 runs in place on z (a tile reads all of its pencils before

@@ -108,12 +108,43 @@ struct fd_batch_s {
   };
   std::vector<StagedLaunch> staged;
   void* sdev = nullptr;
+  size_t sdev_bytes = 0;
   bool use_staged = false;
 };
 
 namespace {
 
 thread_local std::string g_err;
+
+// Device bytes the library holds (plans, batch tables, setup temporaries)
+// and the cap of fd_set_device_limit (0: none). An allocation that would pass
+// the cap fails as on an exhausted device, before hipMalloc is called; the
+// bytes are reserved before the call, so concurrent setups cannot pass the
+// cap together.
+std::atomic<size_t> g_dev_limit{0};
+std::atomic<size_t> g_dev_held{0};
+
+hipError_t dev_alloc(void** ptr, size_t bytes) {
+  *ptr = nullptr;
+  const size_t lim = g_dev_limit.load();
+  size_t cur = g_dev_held.load();
+  do {
+    if (lim && (cur > lim || bytes > lim - cur)) return hipErrorOutOfMemory;
+  } while (!g_dev_held.compare_exchange_weak(cur, cur + bytes));
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    g_dev_held.fetch_sub(bytes);
+  }
+  return e;
+}
+
+hipError_t dev_free(void* ptr, size_t bytes) {
+  if (!ptr) return hipSuccess;
+  const hipError_t e = hipFree(ptr);
+  g_dev_held.fetch_sub(bytes);
+  return e;
+}
 
 struct StageRecord {
   int stage;
@@ -686,10 +717,10 @@ static fd_status batch_upload(fd_batch_s* b) {
   b->stage_seg[kStages] = int(seg.size());
   const size_t db = desc.size() * sizeof(fdk::BatchDesc), sb = seg.size() * sizeof(fdk::BatchSeg);
   if (db + sb > b->dev_cap) {
-    if (b->dev) (void)hipFree(b->dev);
+    (void)dev_free(b->dev, b->dev_cap);
     b->dev = nullptr;
     b->dev_cap = 0;
-    hipError_t e = hipMalloc(&b->dev, db + sb + 256);
+    hipError_t e = dev_alloc(&b->dev, db + sb + 256);
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(FD_E_NOMEM, "fd_batch") : hip_fail(e, "hipMalloc");
     b->dev_cap = db + sb + 256;
   }
@@ -861,7 +892,8 @@ static fd_status batch_build_staged(fd_batch_s* b) {
       }
     }
   }
-  hipError_t e = hipMalloc(&b->sdev, image.size());
+  hipError_t e = dev_alloc(&b->sdev, image.size());
+  if (e == hipSuccess) b->sdev_bytes = image.size();
   if (e != hipSuccess) {
     b->sdev = nullptr;
     b->staged.clear();
@@ -1406,14 +1438,14 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
   }
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) { delete p; return hip_fail(e, "hipGetDevice"); }
-  e = hipMalloc(&p->dev, total);
+  e = dev_alloc(&p->dev, total);
   if (e != hipSuccess) {
     delete p;
     return e == hipErrorOutOfMemory ? fail(FD_E_NOMEM, "fd_setup: device allocation") : hip_fail(e, "hipMalloc");
   }
   e = hipMemcpy(p->dev, host.data(), total, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
-    (void)hipFree(p->dev);
+    (void)dev_free(p->dev, total);
     delete p;
     return hip_fail(e, "hipMemcpy");
   }
@@ -1423,7 +1455,7 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
     size_t sb = 0;
     for (int i = 0; i < ndim; ++i) sb = std::max(sb, stage8[i].size() * sizeof(float));
     void* tmp = nullptr;
-    e = hipMalloc(&tmp, sb);
+    e = dev_alloc(&tmp, sb);
     for (int i = 0; i < ndim && e == hipSuccess; ++i) {
       const int64_t ent = int64_t(fdk::v3_ld(n[i], p->prec)) * fdk::v3_ld(n[i], p->prec);
       e = hipMemcpy(tmp, stage8[i].data(), stage8[i].size() * sizeof(float), hipMemcpyHostToDevice);
@@ -1431,9 +1463,9 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
         e = fdk::fp8s_image(static_cast<const float*>(tmp) + j * ent, base + offv[i][j], ent, nullptr);
       if (e == hipSuccess) e = hipDeviceSynchronize();
     }
-    if (tmp) (void)hipFree(tmp);
+    (void)dev_free(tmp, sb);
     if (e != hipSuccess) {
-      (void)hipFree(p->dev);
+      (void)dev_free(p->dev, total);
       delete p;
       return e == hipErrorOutOfMemory ? fail(FD_E_NOMEM, "fd_setup: device allocation") : hip_fail(e, "FP8 images");
     }
@@ -1459,7 +1491,7 @@ fd_status fd_setup(int32_t ndim, const int32_t* n, const double* const* K, const
 fd_status fd_destroy(fd_plan plan) {
   if (!plan) return FD_OK;
   if (plan->dev) {
-    hipError_t e = hipFree(plan->dev);
+    hipError_t e = dev_free(plan->dev, plan->dev_bytes);
     plan->dev = nullptr;
     delete plan;
     if (e != hipSuccess) return hip_fail(e, "hipFree");
@@ -1472,6 +1504,13 @@ fd_status fd_destroy(fd_plan plan) {
 int64_t fd_plan_size(fd_plan plan) { return plan ? plan->N : 0; }
 
 size_t fd_plan_device_bytes(fd_plan plan) { return plan ? plan->dev_bytes : 0; }
+
+fd_status fd_set_device_limit(size_t bytes) {
+  g_dev_limit.store(bytes);
+  return FD_OK;
+}
+
+size_t fd_device_bytes_held(void) { return g_dev_held.load(); }
 
 size_t fd_workspace_bytes(fd_plan plan, int32_t nrhs) {
   (void)plan;
@@ -1526,7 +1565,7 @@ fd_status fd_setup_mass_banded(int32_t ndim, const int32_t* n, const double* con
     return fail(FD_E_ARG, "fd_setup_mass_banded: prod(n) must be below 2^28");
   }
   hipError_t e = hipGetDevice(&p->device);
-  if (e == hipSuccess) e = hipMalloc(&p->dev, total);
+  if (e == hipSuccess) e = dev_alloc(&p->dev, total);
   if (e != hipSuccess) {
     p->dev = nullptr;
     delete p;
@@ -1609,7 +1648,7 @@ fd_status fd_batch_create(int32_t count, const fd_work* work, fd_batch* out) {
   }
   if (s == FD_OK) s = batch_build_staged(b);
   if (s == FD_OK) {
-    e = hipMalloc(&b->ctl, 256);
+    e = dev_alloc(&b->ctl, 256);
     if (e == hipSuccess) e = hipMemset(b->ctl, 0, 256);
     if (e != hipSuccess) s = hip_fail(e, "fd_batch_create");
   }
@@ -1792,9 +1831,9 @@ fd_status fd_batch_check(fd_batch b) {
 
 fd_status fd_batch_destroy(fd_batch b) {
   if (!b) return FD_OK;
-  if (b->dev) (void)hipFree(b->dev);
-  if (b->ctl) (void)hipFree(b->ctl);
-  if (b->sdev) (void)hipFree(b->sdev);
+  (void)dev_free(b->dev, b->dev_cap);
+  (void)dev_free(b->ctl, 256);
+  (void)dev_free(b->sdev, b->sdev_bytes);
   delete b;
   return FD_OK;
 }

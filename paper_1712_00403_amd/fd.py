@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "FD_OK", 1: "FD_E_ARG", 2: "FD_E_NOTSPD", 3: "FD_E_NOMEM", 4:
 # every symbol declared in include/fd.h
 EXPORTS = ("fd_assemble_1d", "fd_nitsche_stiffness_1d", "fd_mixed_1d", "fd_quadrature_1d", "fd_factor_1d", "fd_geometry_coefficients",
            "fd_separable_factors", "fd_operator_diagonal", "fd_setup", "fd_setup_mass_banded", "fd_destroy",
-           "fd_plan_size", "fd_plan_device_bytes", "fd_workspace_bytes", "fd_plan_factors", "fd_apply",
+           "fd_plan_size", "fd_plan_device_bytes", "fd_set_device_limit", "fd_device_bytes_held", "fd_workspace_bytes", "fd_plan_factors", "fd_apply",
            "fd_apply_batched", "fd_batch_create", "fd_batch_apply", "fd_batch_tune", "fd_batch_set_config",
            "fd_batch_info", "fd_batch_signature", "fd_batch_check", "fd_batch_destroy", "fd_apply_persistent_static", "fd_timing_enable", "fd_timing_read", "fd_timing_launches", "fd_last_error")
 
@@ -78,6 +78,10 @@ def lib():
     L.fd_plan_size.restype = ctypes.c_int64
     L.fd_plan_device_bytes.argtypes = [ctypes.c_void_p]
     L.fd_plan_device_bytes.restype = ctypes.c_size_t
+    L.fd_set_device_limit.argtypes = [ctypes.c_size_t]
+    L.fd_set_device_limit.restype = ctypes.c_int
+    L.fd_device_bytes_held.argtypes = []
+    L.fd_device_bytes_held.restype = ctypes.c_size_t
     L.fd_workspace_bytes.argtypes = [ctypes.c_void_p, ctypes.c_int32]
     L.fd_workspace_bytes.restype = ctypes.c_size_t
     L.fd_plan_factors.argtypes = [ctypes.c_void_p, ctypes.c_int32, c_dp, c_dp]
@@ -115,6 +119,16 @@ def lib():
 def _check(status):
     if status != FD_OK:
         raise FDError(status, lib().fd_last_error().decode())
+
+
+def set_device_limit(nbytes):
+    """Cap the device bytes the library holds at once (0: no cap); setups past it raise FD_E_NOMEM."""
+    _check(lib().fd_set_device_limit(int(nbytes)))
+
+
+def device_bytes_held():
+    """Device bytes the library holds now (plans, fixed-batch tables)."""
+    return int(lib().fd_device_bytes_held())
 
 
 def _dp(a):

@@ -44,15 +44,21 @@ class BlockPreconditioner:
         self.precision = precision
         self.plans = []
         self.sizes = []
-        for bi, spec in enumerate(problem.blocks):
-            Ks, Ms = factors[bi] if factors is not None else block_factors(spec)
-            dt = None if diag_targets is None else diag_targets[bi]
-            w = np.asarray(spec.weights if weights is None else weights[bi], dtype=np.float64)
-            banded = pressure == "banded" and Ks is None and dt is None
-            plan = fd.Plan(Ks, Ms, weights=None if banded else w, diag_target=dt, precision=precision,
-                           banded=banded)
-            self.plans.append(plan)
-            self.sizes.append(plan.N)
+        try:
+            for bi, spec in enumerate(problem.blocks):
+                Ks, Ms = factors[bi] if factors is not None else block_factors(spec)
+                dt = None if diag_targets is None else diag_targets[bi]
+                w = np.asarray(spec.weights if weights is None else weights[bi], dtype=np.float64)
+                banded = pressure == "banded" and Ks is None and dt is None
+                plan = fd.Plan(Ks, Ms, weights=None if banded else w, diag_target=dt, precision=precision,
+                               banded=banded)
+                self.plans.append(plan)
+                self.sizes.append(plan.N)
+        except BaseException:
+            # a block that fails (a device-memory cap, an exhausted device)
+            # releases the plans of the blocks before it at once
+            self.close()
+            raise
         self.offsets = np.concatenate([[0], np.cumsum(self.sizes)]).astype(np.int64)
         self.N = int(self.offsets[-1])
         self.io_dtype = self.plans[0].io_dtype

@@ -154,3 +154,11 @@ def test_mixed_integrals_match_oracle(fd, n_el, p):
     np.testing.assert_allclose(fd.mixed_1d(n_el, p + 1, p - 1, 1, p + 1, p - 1, 1), K, rtol=0, atol=1e-12)
     with pytest.raises(fd.FDError):
         fd.mixed_1d(n_el, p, p - 1, 2, p, p - 1, 0)
+
+
+def test_device_limit_entry_points_without_allocations(fd):
+    # (no device here: nothing is held, and setting or clearing the cap always succeeds)
+    assert fd.device_bytes_held() == 0
+    fd.set_device_limit(1 << 20)
+    fd.set_device_limit(0)
+    assert fd.device_bytes_held() == 0
