@@ -3,6 +3,8 @@
 The cap stands in for an exhausted device, so the FD_E_NOMEM paths of
 fd_setup and fd_batch_create run without filling the GPU.
 """
+import gc
+
 import numpy as np
 import pytest
 import torch
@@ -19,6 +21,9 @@ NOMEM = 3
 
 @pytest.fixture
 def capped():
+    # plans that earlier tests left to the garbage collector are freed now, so
+    # that none is released (and the held bytes change) in the middle of a test
+    gc.collect()
     yield
     fd.set_device_limit(0)
 
